@@ -1,0 +1,222 @@
+/*
+ * ma.h -- C ABI of the MI355X FAS multigrid solver for the 3D Monge-Ampere
+ * equation  det(D^2 u) = f > 0  in the unit cube,  u = g  on its boundary,
+ * u convex  (Liu, Froese, Oberman, Xiao, "A multigrid scheme for 3D
+ * Monge-Ampere equations", Section 1, eqs. 1.1-1.2).
+ *
+ * Grid and layout (Section 2): h = 1/n, nodes x_i = i h, i = 0..n in each
+ * direction.  Every grid function is one contiguous array of (n+1)^3 doubles
+ * in DEVICE memory, x fastest: index(i,j,k) = i + (n+1)*(j + (n+1)*k).  Nodes
+ * with any index in {0, n} are Dirichlet nodes: the solver reads them and
+ * never writes them.
+ *
+ * Ownership: the caller owns u and f (device pointers, e.g. torch tensors);
+ * a solver owns every scratch array of its multigrid hierarchy from
+ * ma_create to ma_destroy.  All device work is ordered on the HIP stream
+ * given to ma_create (or ma_set_stream); functions that return a number to
+ * the host (norms, reports) synchronise that stream.
+ *
+ * Errors: no function throws or aborts.  Each returns an ma_status and keeps
+ * a message readable through ma_last_error(solver).  A solver is not
+ * thread-safe: use it from one host thread at a time.
+ */
+#ifndef MA_H
+#define MA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ma_solver ma_solver;
+typedef struct ma_batch ma_batch;
+
+typedef enum {
+    MA_OK = 0,
+    MA_ERR_ARG = 1,            /* invalid argument (sizes, null pointers)      */
+    MA_ERR_OOM = 2,            /* device allocation failed                     */
+    MA_ERR_DEVICE = 3,         /* a HIP call or kernel launch failed           */
+    MA_ERR_NOT_CONVERGED = 4,  /* max_cycles spent; the report is still filled */
+    MA_ERR_NONFINITE = 5       /* a residual norm became NaN or Inf            */
+} ma_status;
+
+typedef enum { MA_FP64 = 0, MA_MIXED = 1 } ma_precision;
+
+/* Multicolour orderings of the nonlinear Gauss-Seidel sweep.  The 19-point
+ * stencil (Section 2, eqs. 2.1-2.6) needs four or more colours to decouple:
+ *   MA_COLOR4: colour = ((i+j) mod 2) + 2 ((i+k) mod 2), phases 0..3;
+ *   MA_COLOR8: colour = (i mod 2) + 2 (j mod 2) + 4 (k mod 2), phases 0..7. */
+typedef enum { MA_COLOR4 = 0, MA_COLOR8 = 1 } ma_order;
+
+/* Residual restriction I_h^H of Algorithm 1 step 3.  Section 3 gives the
+ * 7-point half-weighting and allows other operators; with multicolour
+ * Gauss-Seidel the half-weighted V-cycle does not contract, so full
+ * weighting (27 points, tensor product of 1/4, 1/2, 1/4) is the default. */
+typedef enum { MA_RESTRICT_FULL = 0, MA_RESTRICT_HALF = 1 } ma_restriction;
+
+/* Smoother kernel selection (same arithmetic, different data movement). */
+typedef enum {
+    MA_SMOOTHER_AUTO = 0,      /* fused where available, else per colour        */
+    MA_SMOOTHER_COLOR = 1,     /* one in-place launch per colour phase          */
+    MA_SMOOTHER_FUSED = 2      /* all colour phases of a sweep in one launch     */
+} ma_smoother;
+
+/* ma_solve flag: replace the interior of u by the initial guess that solves
+ * Lap_h u0 = 3 f^{1/3} with the Dirichlet data of u (7-point Laplacian,
+ * linear V-cycles with the same ordering and transfers). */
+#define MA_INIT_POISSON 1u
+
+typedef struct {
+    int n;                 /* intervals per side, n >= 2; grid (n+1)^3, h = 1/n  */
+    int nu1, nu2, nu0;     /* pre-, post-smoothing sweeps, sweeps on the coarsest
+                              grid (Algorithm 1; Section 4 uses 2, 2, 1)         */
+    int order;             /* ma_order                                           */
+    int restriction;       /* ma_restriction                                     */
+    int precision;         /* ma_precision                                       */
+    int smoother;          /* ma_smoother                                        */
+    int max_cycles;        /* V-cycles (MA_FP64) or outer corrections (MA_MIXED) */
+    double tol;            /* default relative discrete-L2 residual (Section 4)  */
+    double init_tol;       /* relative linear residual for MA_INIT_POISSON       */
+    int init_max_cycles;   /* cap on the linear V-cycles of MA_INIT_POISSON      */
+    int inner_cycles;      /* MA_MIXED: FP32 V-cycles per outer correction       */
+    int profile;           /* 1: time finest-level smoothing with HIP events     */
+} ma_params;
+
+typedef struct {
+    int cycles;            /* FAS V-cycles run (MA_MIXED: FP32 inner cycles)     */
+    int outer;             /* MA_MIXED outer FP64 corrections (0 for MA_FP64)    */
+    int init_cycles;       /* linear V-cycles of the Poisson initial guess       */
+    int converged;         /* 1 when res <= tol * res0                           */
+    double res0;           /* discrete L2 residual sqrt(h^3 sum r^2) of u0       */
+    double res;            /* final discrete L2 residual                         */
+    double rel_res;        /* res / res0                                         */
+    long long nonconvex;   /* point updates with F <= 0 or a non-SPD Hessian     */
+    long long fp64_fallbacks; /* MA_MIXED nodes recomputed in FP64               */
+    double seconds;        /* wall time of the call                              */
+    double point_updates;  /* nonlinear GS point updates performed               */
+    double alg_bytes;      /* algorithmic HBM bytes of the kernels launched      */
+    double history[64];    /* residual after each cycle (first 64)              */
+    /* params.profile = 1 only: finest-level smoother launches, their total
+     * device time (HIP events on the solver's stream) and algorithmic bytes
+     * (24 B per interior node per FP64 sweep: read u, read f, write u). */
+    int smooth_launches;
+    double smooth_seconds;
+    double smooth_bytes;
+} ma_report;
+
+/* Fill p with the defaults for an n-interval grid: V(2,2), one coarsest
+ * sweep, 4 colours, full weighting, FP64, auto smoother, 100 cycles,
+ * tol 1e-8, Poisson guess to 1e-6 relative in at most 30 cycles. */
+void ma_params_default(ma_params *p, int n);
+
+/* Device bytes ma_create would allocate for p (0 if p is invalid).  Does not
+ * allocate; used for admission against an HBM budget. */
+size_t ma_footprint_bytes(const ma_params *p);
+
+/* Number of multigrid levels for n: n_0 = n, n_{l+1} = n_l / 2 while n_l is
+ * even and >= 4, so the coarsest grid has n_L = 2 (one unknown, h0 = 1/2 as
+ * in Section 4) or an odd n_L >= 3.  Writes up to cap sizes into ns. */
+int ma_levels(int n, int *ns, int cap);
+
+/* Create a solver for p on the current HIP device; hip_stream is a
+ * hipStream_t (NULL = default stream).  MA_ERR_ARG for invalid p,
+ * MA_ERR_OOM when the hierarchy does not fit. */
+ma_status ma_create(const ma_params *p, void *hip_stream, ma_solver **out);
+
+/* Release the hierarchy; s may be NULL. */
+void ma_destroy(ma_solver *s);
+
+/* Message of the last failed call on s (or of the last failed ma_create when
+ * s is NULL).  Valid until the next call on s. */
+const char *ma_last_error(const ma_solver *s);
+
+/* Order later work on another hipStream_t. */
+ma_status ma_set_stream(ma_solver *s, void *hip_stream);
+
+/* Solve det(D^2 u) = f (Algorithm 1 repeated under the stopping rule of
+ * Section 4): run V(nu1,nu2) cycles until the discrete L2 residual is
+ * <= tol * res0 (tol <= 0 selects params.tol), res0 being the residual of
+ * the initial guess.  u: device (n+1)^3, Dirichlet layer = g, interior = the
+ * initial guess on entry (or replaced when flags has MA_INIT_POISSON) and
+ * the solution on exit.  f: device (n+1)^3, interior read.  rep may be NULL.
+ * Returns MA_ERR_NOT_CONVERGED when max_cycles run out (u holds the last
+ * iterate), MA_ERR_NONFINITE when a norm is not finite. */
+ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigned flags,
+                   ma_report *rep);
+
+/* One FAS V(nu1,nu2) cycle of Algorithm 1 on u in place (asynchronous). */
+ma_status ma_vcycle(ma_solver *s, double *u, const double *f);
+
+/* Residual r = f - det(D^2_h u) at interior nodes (r = 0 on the Dirichlet
+ * layer), the discrete Monge-Ampere operator of Section 1 / eq. 2.7.
+ * r_or_null: device (n+1)^3 output or NULL.  l2_host (may be NULL): host
+ * double receiving sqrt(h^3 sum r^2); synchronises the stream when given. */
+ma_status ma_residual(ma_solver *s, const double *u, const double *f, double *r_or_null,
+                      double *l2_host);
+
+/* count nonlinear Gauss-Seidel sweeps (Section 2, eqs. 2.8-2.9: each point
+ * takes the smallest real root of its local cubic) on the finest grid, in
+ * the solver's colour ordering.  u in place, f read.  nonconvex_host (may be
+ * NULL) receives the number of updates that were not certified convex. */
+ma_status ma_sweep(ma_solver *s, double *u, const double *f, int count,
+                   long long *nonconvex_host);
+
+/* FAS restriction from the finest grid (n) to the next (n/2), Algorithm 1
+ * steps 3-5: w_c = injection of u (all coarse nodes), b_c = S_H(w_c) +
+ * I_h^H (f - S_h(u)) at coarse interior nodes, 0 on the coarse boundary.
+ * u, f: device (n+1)^3; w_c, b_c: device (n/2+1)^3 outputs.  MA_ERR_ARG if n
+ * is odd or n < 4. */
+ma_status ma_restrict(ma_solver *s, const double *u, const double *f, double *w_c,
+                      double *b_c);
+
+/* Coarse-grid correction, Algorithm 1 steps 7-8: u += I_H^h (u_c - w_c) at
+ * fine interior nodes, trilinear interpolation (weights 1, 1/2, 1/4, 1/8).
+ * u: device (n+1)^3 in place; u_c, w_c: device (n/2+1)^3. */
+ma_status ma_prolong_correct(ma_solver *s, double *u, const double *u_c, const double *w_c);
+
+/* The MA_INIT_POISSON initial guess alone: linear V-cycles on
+ * Lap_h u = 3 f^{1/3} until the relative linear residual is <= init_tol or
+ * init_max_cycles ran.  cycles_host (may be NULL) receives the cycle count. */
+ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_host);
+
+/* ---------------------------------------------------------------------- */
+/* Batched solves: many independent problems of different sizes advance     */
+/* together, one launch per level phase for all of them.                    */
+/* ---------------------------------------------------------------------- */
+
+/* Solve count independent problems together.  solvers[i] must have been
+ * created for the size of u[i], f[i] and all with the same precision,
+ * ordering and smoothing counts.  Each result equals that of ma_solve on
+ * the same solver alone.  reps (may be NULL) receives count reports.  Returns
+ * the first non-OK status over the solves (all solves still complete). */
+ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const double *const *f,
+                         int count, double tol, unsigned flags, ma_report *reps);
+
+/* A resident batch for continuous serving: solves join and leave between
+ * ticks; one tick runs one V-cycle (MA_MIXED: one outer correction) of every
+ * active solve, batched by level.  The batch does not own the solvers. */
+ma_status ma_batch_create(int max_solves, void *hip_stream, ma_batch **out);
+void ma_batch_destroy(ma_batch *b);
+const char *ma_batch_last_error(const ma_batch *b);
+
+/* Join: prepares u (Poisson guess when flags has MA_INIT_POISSON) and
+ * computes res0 on the batch's stream.  *slot_out receives the slot id. */
+ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, double tol,
+                       unsigned flags, int *slot_out);
+
+/* One tick over all active slots; done_out[slot] (host, max_solves entries,
+ * may be NULL) is set to 1 for slots that converged or failed this tick. */
+ma_status ma_batch_tick(ma_batch *b, int *done_out);
+
+/* Report of a slot (valid while it is in the batch). */
+ma_status ma_batch_report(const ma_batch *b, int slot, ma_report *rep);
+
+/* Leave: frees the slot for another solve. */
+ma_status ma_batch_remove(ma_batch *b, int slot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MA_H */

@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, every
+symbol declared in include/ma.h is exported, and the pure host entry points
+(defaults, level hierarchy, footprint, argument validation) behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ma.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ma_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = _declared()
+    for n in ("ma_create", "ma_solve", "ma_residual", "ma_vcycle", "ma_destroy",
+              "ma_footprint_bytes", "ma_solve_batch", "ma_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1411_7018_amd import _lib
+    L = _lib.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert missing == []
+    assert set(_lib.EXPORTS) == set(_declared())
+
+
+def test_defaults_and_levels():
+    from paper_1411_7018_amd import _lib as L
+    p = L.ma_params_default(128)
+    assert (p.n, p.nu1, p.nu2, p.nu0) == (128, 2, 2, 1)
+    assert p.order == L.MA_COLOR4 and p.restriction == L.MA_RESTRICT_FULL
+    assert p.tol == 1e-8
+    assert L.ma_levels(16) == [16, 8, 4, 2]
+    assert L.ma_levels(384) == [384, 192, 96, 48, 24, 12, 6, 3]
+    assert L.ma_levels(7) == [7]
+
+
+def test_levels_match_oracle():
+    import oracle
+    from paper_1411_7018_amd import _lib as L
+    for n in (2, 3, 4, 6, 16, 33, 96, 100, 128, 384):
+        assert L.ma_levels(n) == oracle.levels(n)
+
+
+def test_footprint_grows_with_n_and_rejects_invalid():
+    from paper_1411_7018_amd import _lib as L
+    a = L.ma_footprint_bytes(L.ma_params_default(64))
+    b = L.ma_footprint_bytes(L.ma_params_default(128))
+    assert 0 < a < b
+    # the hierarchy holds the fine residual, the Poisson RHS and the sweep
+    # target (3 fine arrays) plus 5 arrays per coarse level
+    n = 128
+    fine = (n + 1) ** 3 * 8
+    assert 3 * fine <= b <= 3 * fine + 5 * 8 * sum((m + 1) ** 3 for m in L.ma_levels(n)[1:]) + 2**22
+    bad = L.ma_params_default(1)
+    assert L.ma_footprint_bytes(bad) == 0
+
+
+def test_create_rejects_invalid_params_without_gpu():
+    from paper_1411_7018_amd import _lib as L
+    for field, val in (("n", 1), ("nu0", 0), ("order", 7), ("precision", 9),
+                       ("restriction", 5), ("inner_cycles", 0)):
+        p = L.ma_params_default(16)
+        setattr(p, field, val)
+        with pytest.raises(L.MAError) as ei:
+            L.ma_create(p, None)
+        assert ei.value.status == L.MA_ERR_ARG
+    assert "n must be" in L.ma_last_error(None) or L.ma_last_error(None)
+
+
+def test_null_handles_are_rejected():
+    from paper_1411_7018_amd import _lib as L
+    lib = L.lib()
+    assert lib.ma_solve(None, None, None, 0.0, 0, None) == L.MA_ERR_ARG
+    assert lib.ma_vcycle(None, None, None) == L.MA_ERR_ARG
+    assert lib.ma_batch_tick(None, None) == L.MA_ERR_ARG
+    assert lib.ma_solve_batch(None, None, None, -1, 0.0, 0, None) == L.MA_ERR_ARG
+    lib.ma_destroy(None)
+    out = ctypes.c_void_p()
+    assert lib.ma_batch_create(0, None, ctypes.byref(out)) == L.MA_ERR_ARG
