@@ -81,6 +81,8 @@ typedef struct {
     int init_max_cycles;   /* cap on the linear V-cycles of MA_INIT_POISSON      */
     int inner_cycles;      /* MA_MIXED: FP32 V-cycles per outer correction       */
     int profile;           /* 1: time finest-level smoothing with HIP events     */
+    int tile_config;       /* fused sweep tile shape: 0 automatic, 1..6 fixed    */
+    int zchunk;            /* fused sweep planes per z-chunk: 0 automatic        */
 } ma_params;
 
 typedef struct {

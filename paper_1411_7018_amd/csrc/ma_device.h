@@ -12,38 +12,59 @@ struct Hess {
     double xx, yy, zz, xy, xz, yz;
 };
 
-// Hessian at linear index p of an x-fastest array with strides (sx, sy, sz);
-// s = 1/h^2, s4 = 1/(4h^2) for the grid step h those strides span.  Second differences are taken as
-// differences of first differences, which are exact (Sterbenz) when the
-// neighbouring values are close; this keeps round-off at the scale of the
-// first differences instead of |u|.
+// Discrete Hessian at a node from three pointers at that node's position in
+// the planes k-1 (D), k (C) and k+1 (U).  Inside a plane, C[xp] / C[xm] are
+// the x+1 / x-1 neighbours and C[sy] / C[-sy] the y+1 / y-1 neighbours
+// (xp = 1, xm = -1 for plain x-fastest storage; other values for layouts
+// that de-interleave even and odd x).  s = 1/h^2, s4 = 1/(4h^2).  Second
+// differences are taken as differences of first differences, exact
+// (Sterbenz) when neighbouring values are close, which keeps round-off at
+// the scale of the first differences instead of |u|.  Every smoother,
+// residual and restriction kernel evaluates the Hessian through this one
+// expression tree, so the same neighbour values give bitwise equal results.
+template <typename T>
+__device__ __forceinline__ Hess hessian3(const T *__restrict__ D, const T *__restrict__ C,
+                                        const T *__restrict__ U, long xp, long xm, long sy,
+                                        double s, double s4)
+{
+    const double c = C[0];
+    Hess g;
+    g.xx = ((double(C[xp]) - c) - (c - double(C[xm]))) * s;
+    g.yy = ((double(C[sy]) - c) - (c - double(C[-sy]))) * s;
+    g.zz = ((double(U[0]) - c) - (c - double(D[0]))) * s;
+    g.xy = ((double(C[xp + sy]) - double(C[xm + sy])) - (double(C[xp - sy]) - double(C[xm - sy])))
+           * s4;
+    g.xz = ((double(U[xp]) - double(U[xm])) - (double(D[xp]) - double(D[xm]))) * s4;
+    g.yz = ((double(U[sy]) - double(U[-sy])) - (double(D[sy]) - double(D[-sy]))) * s4;
+    return g;
+}
+
+// Hessian at linear index p of an x-fastest array with strides (sx, sy, sz).
 template <typename T>
 __device__ __forceinline__ Hess hessian_at(const T *__restrict__ u, long p, long sx, long sy,
                                            long sz, double s, double s4)
 {
-    const double c = u[p];
-    Hess g;
-    g.xx = ((double(u[p + sx]) - c) - (c - double(u[p - sx]))) * s;
-    g.yy = ((double(u[p + sy]) - c) - (c - double(u[p - sy]))) * s;
-    g.zz = ((double(u[p + sz]) - c) - (c - double(u[p - sz]))) * s;
-    g.xy = ((double(u[p + sx + sy]) - double(u[p - sx + sy]))
-            - (double(u[p + sx - sy]) - double(u[p - sx - sy]))) * s4;
-    g.xz = ((double(u[p + sx + sz]) - double(u[p - sx + sz]))
-            - (double(u[p + sx - sz]) - double(u[p - sx - sz]))) * s4;
-    g.yz = ((double(u[p + sy + sz]) - double(u[p - sy + sz]))
-            - (double(u[p + sy - sz]) - double(u[p - sy - sz]))) * s4;
-    return g;
+    return hessian3(u + p - sz, u + p, u + p + sz, sx, -sx, sy, s, s4);
 }
 
-// 7-point Laplacian from differences of first differences.
+// 7-point Laplacian from differences of first differences (same pointer
+// and offset convention as hessian3).
+template <typename T>
+__device__ __forceinline__ double laplacian3(const T *__restrict__ D, const T *__restrict__ C,
+                                             const T *__restrict__ U, long xp, long xm, long sy,
+                                             double s)
+{
+    const double c = C[0];
+    return (((double(C[xp]) - c) - (c - double(C[xm])))
+            + ((double(C[sy]) - c) - (c - double(C[-sy])))
+            + ((double(U[0]) - c) - (c - double(D[0])))) * s;
+}
+
 template <typename T>
 __device__ __forceinline__ double laplacian_at(const T *__restrict__ u, long p, long sx, long sy,
                                                long sz, double s)
 {
-    const double c = u[p];
-    return (((double(u[p + sx]) - c) - (c - double(u[p - sx])))
-            + ((double(u[p + sy]) - c) - (c - double(u[p - sy])))
-            + ((double(u[p + sz]) - c) - (c - double(u[p - sz])))) * s;
+    return laplacian3(u + p - sz, u + p, u + p + sz, sx, -sx, sy, s);
 }
 
 __device__ __forceinline__ double det3(const Hess &g)
@@ -120,8 +141,11 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
 // lands on the left of the root.  Start: sig = 0 when G is SPD (Sylvester
 // minors), else a Gershgorin lower bound of lambda_min minus F^{1/3}, where
 // q >= 0 (the left end of the Theorem 2.2 bracket or further left).
-// Stop when the step is below 1e-9 of the eigenvalue scale: the error after
-// that step is O(step^2 / scale), i.e. at round-off.
+// The Newton quotient uses the hardware reciprocal refined by one
+// Newton-Raphson step (relative error ~1e-16); an inexact quotient only
+// perturbs the iteration, not its limit.  Stop when the step is below 1e-9 of
+// the eigenvalue scale: the error after that step is O(step^2 / scale), i.e.
+// at round-off.
 //
 // nonconvex is set when F <= 0 or the result is not finite; such nodes take
 // the general closed form.
@@ -143,13 +167,15 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         sig = fmin(lx, fmin(ly, lz)) - cbrt(F);
     }
     const double c0 = I3 - F;
-    const double scale = fabs(I1) + fabs(sig);
+    const double thr = 1e-9 * (fabs(I1) + fabs(sig));
     for (int it = 0; it < 64; ++it) {
         const double q = ((I1 - sig) * sig - I2) * sig + c0;
         const double dq = (2.0 * I1 - 3.0 * sig) * sig - I2;
-        const double d = q / dq;
+        double r = __builtin_amdgcn_rcp(dq);
+        r = fma(r, fma(-dq, r, 1.0), r);
+        const double d = q * r;
         sig -= d;
-        if (!(fabs(d) > 1e-9 * (scale + fabs(sig))))
+        if (!(fabs(d) > thr))
             break;
     }
     if (!isfinite(sig)) {
@@ -157,6 +183,34 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         return smallest_root_general(g, F);
     }
     return sig;
+}
+
+// New centre value of one nonlinear Gauss-Seidel update (eq. 2.9 in the
+// shifted form): u_p + sigma* h^2 / 2, with half_h2 = 0.5 / s = h^2 / 2
+// computed once on the host.
+__device__ __forceinline__ double ma_point_update(const Hess &g, double c, double F,
+                                                  double half_h2, bool &nonconvex)
+{
+    const double sig = smallest_root(g, F, nonconvex);
+    return c + sig * half_h2;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip.  Map block
+// b of nb to work item tile_of_block(b, nb) so that every XCD gets a
+// contiguous range of work items: neighbouring rows / tiles, which read each
+// other's data as stencil halos, then share one L2.
+__device__ __forceinline__ int tile_of_block(int b, int nb)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = nb >> 3, rem = nb & 7;
+    return xcd * q + min(xcd, rem) + idx;
+}
+
+// New centre value of one linear Gauss-Seidel update for Lap_h u = F;
+// inv6s = 1 / (6 s) computed once on the host.
+__device__ __forceinline__ double lap_point_update(double lap, double c, double F, double inv6s)
+{
+    return c - (F - lap) * inv6s;
 }
 
 } // namespace mafas

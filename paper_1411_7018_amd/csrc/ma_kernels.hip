@@ -47,21 +47,25 @@ __device__ __forceinline__ double block_sum(double v)
 template <int OP, int ORDER>
 __global__ __launch_bounds__(64) void k_sweep_color(double *__restrict__ u,
                                                     const double *__restrict__ F, int n,
-                                                    int color, double s, double s4,
+                                                    int color, int gx, int gy, int nb, double s,
+                                                    double s4, double hk,
                                                     unsigned long long *__restrict__ ncount)
 {
+    // one block = 64 colour nodes of one x-row; rows in XCD-contiguous order
+    const int tile = tile_of_block(blockIdx.x, nb);
+    const int bx = tile % gx, rest = tile / gx, by = rest % gy, bz = rest / gy;
     int i0, j, k;
     if (ORDER == 0) {
         const int c0 = color & 1, c1 = color >> 1;
-        j = 1 + blockIdx.y;
-        k = (((c0 + c1 + j) & 1) ? 1 : 2) + 2 * blockIdx.z;
+        j = 1 + by;
+        k = (((c0 + c1 + j) & 1) ? 1 : 2) + 2 * bz;
         i0 = ((c0 + j) & 1) ? 1 : 2;
     } else {
-        j = ((color >> 1) & 1 ? 1 : 2) + 2 * blockIdx.y;
-        k = ((color >> 2) & 1 ? 1 : 2) + 2 * blockIdx.z;
+        j = ((color >> 1) & 1 ? 1 : 2) + 2 * by;
+        k = ((color >> 2) & 1 ? 1 : 2) + 2 * bz;
         i0 = (color & 1) ? 1 : 2;
     }
-    const int i = i0 + 2 * (blockIdx.x * 64 + threadIdx.x);
+    const int i = i0 + 2 * (bx * 64 + int(threadIdx.x));
     if (i > n - 1 || j > n - 1 || k > n - 1)
         return;
     const long sy = n + 1, sz = sy * sy;
@@ -69,13 +73,11 @@ __global__ __launch_bounds__(64) void k_sweep_color(double *__restrict__ u,
     if (OP == OP_MA) {
         const Hess g = hessian_at(u, p, 1, sy, sz, s, s4);
         bool nc = false;
-        const double sig = smallest_root(g, F[p], nc);
-        u[p] = u[p] + sig * (0.5 / s);
+        u[p] = ma_point_update(g, u[p], F[p], hk, nc);
         if (nc && ncount)
             atomicAdd(ncount, 1ull);
     } else {
-        const double lap = laplacian_at(u, p, 1, sy, sz, s);
-        u[p] = u[p] - (F[p] - lap) * (1.0 / (6.0 * s));
+        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, s), u[p], F[p], hk);
     }
 }
 
@@ -249,28 +251,27 @@ hipError_t launch_sweep_color(hipStream_t st, int op, int order, int n, double *
                               const double *F, unsigned long long *nonconvex)
 {
     const double s = double(n) * double(n), s4 = 0.25 * s;
+    const double hk = op == OP_MA ? 0.5 / s : 1.0 / (6.0 * s);
     const int ncol = order == 1 ? 8 : 4;
+    const int gx = ((n + 1) / 2 + 63) / 64;
+    const int gy = order == 0 ? n - 1 : n / 2, gz = n / 2;
+    const int nb = gx * gy * gz;
     for (int c = 0; c < ncol; ++c) {
-        dim3 grid;
-        if (order == 0)
-            grid = dim3(((n + 1) / 2 + 63) / 64, n - 1, n / 2);
-        else
-            grid = dim3(((n + 1) / 2 + 63) / 64, n / 2, n / 2);
+#define MA_COLOR_LAUNCH(OPV, ORD)                                                                \
+    hipLaunchKernelGGL((k_sweep_color<OPV, ORD>), dim3(nb), dim3(64), 0, st, u, F, n, c, gx, gy,  \
+                       nb, s, s4, hk, nonconvex)
         if (op == OP_MA) {
             if (order == 0)
-                hipLaunchKernelGGL((k_sweep_color<OP_MA, 0>), grid, dim3(64), 0, st, u, F, n, c, s,
-                                   s4, nonconvex);
+                MA_COLOR_LAUNCH(OP_MA, 0);
             else
-                hipLaunchKernelGGL((k_sweep_color<OP_MA, 1>), grid, dim3(64), 0, st, u, F, n, c, s,
-                                   s4, nonconvex);
+                MA_COLOR_LAUNCH(OP_MA, 1);
         } else {
             if (order == 0)
-                hipLaunchKernelGGL((k_sweep_color<OP_LAP, 0>), grid, dim3(64), 0, st, u, F, n, c,
-                                   s, s4, nonconvex);
+                MA_COLOR_LAUNCH(OP_LAP, 0);
             else
-                hipLaunchKernelGGL((k_sweep_color<OP_LAP, 1>), grid, dim3(64), 0, st, u, F, n, c,
-                                   s, s4, nonconvex);
+                MA_COLOR_LAUNCH(OP_LAP, 1);
         }
+#undef MA_COLOR_LAUNCH
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -377,14 +378,6 @@ hipError_t launch_fill_u64(hipStream_t st, size_t count, unsigned long long v,
     hipLaunchKernelGGL(k_fill<unsigned long long>, dim3((count + 255) / 256), dim3(256), 0, st, dst,
                        count, v);
     return hipGetLastError();
-}
-
-bool fused_supported(int) { return false; }
-
-hipError_t launch_sweep_fused(hipStream_t, int, int, const double *, double *, const double *,
-                              unsigned long long *)
-{
-    return hipErrorNotSupported;
 }
 
 } // namespace mafas

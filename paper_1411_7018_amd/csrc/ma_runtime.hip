@@ -51,6 +51,10 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "unknown smoother";
         return false;
     }
+    if (p->tile_config < 0 || p->tile_config > fused_num_configs() || p->zchunk < 0) {
+        why = "tile_config must be 0..fused_num_configs() and zchunk >= 0";
+        return false;
+    }
     if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1) {
         why = "cycle counts must be >= 0 (inner_cycles >= 1)";
         return false;
@@ -365,6 +369,8 @@ bool ma_solver::use_fused(int l) const
 {
     if (p.order != MA_COLOR4 || p.smoother == MA_SMOOTHER_COLOR)
         return false;
+    if (p.smoother == MA_SMOOTHER_FUSED)
+        return lv[l].n >= 4;
     return fused_supported(lv[l].n);
 }
 
@@ -409,8 +415,10 @@ ma_status ma_solver::smooth(int l, double *u, const double *F, int count, int op
         double *t = lv[l].t;
         MA_HIP(this, launch_copy_boundary(stream, n, u, t));
         for (; done + 2 <= count; done += 2) {
-            MA_HIP(this, launch_sweep_fused(stream, op, n, u, t, F, dcount));
-            MA_HIP(this, launch_sweep_fused(stream, op, n, t, u, F, dcount));
+            MA_HIP(this, launch_sweep_fused(stream, op, n, u, t, F, dcount, p.tile_config - 1,
+                                            p.zchunk));
+            MA_HIP(this, launch_sweep_fused(stream, op, n, t, u, F, dcount, p.tile_config - 1,
+                                            p.zchunk));
         }
     }
     const int fused_launches = done;
