@@ -83,6 +83,7 @@ typedef struct {
     int profile;           /* 1: time finest-level smoothing with HIP events     */
     int tile_config;       /* fused sweep tile shape: 0 automatic, 1..6 fixed    */
     int zchunk;            /* fused sweep planes per z-chunk: 0 automatic        */
+    int graphs;            /* 1: replay each cycle from a captured hipGraph      */
 } ma_params;
 
 typedef struct {
@@ -109,7 +110,8 @@ typedef struct {
 
 /* Fill p with the defaults for an n-interval grid: V(2,2), one coarsest
  * sweep, 4 colours, full weighting, FP64, auto smoother, 100 cycles,
- * tol 1e-8, Poisson guess to 1e-6 relative in at most 30 cycles. */
+ * tol 1e-8, Poisson guess to 1e-6 relative in at most 30 cycles, two FP32
+ * cycles per mixed correction, hipGraph replay on. */
 void ma_params_default(ma_params *p, int n);
 
 /* Device bytes ma_create would allocate for p (0 if p is invalid).  Does not
@@ -147,7 +149,8 @@ ma_status ma_set_stream(ma_solver *s, void *hip_stream);
 ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigned flags,
                    ma_report *rep);
 
-/* One FAS V(nu1,nu2) cycle of Algorithm 1 on u in place (asynchronous). */
+/* One FAS V(nu1,nu2) cycle of Algorithm 1 on u in place (MA_FP64 solvers);
+ * returns once the cycle has run. */
 ma_status ma_vcycle(ma_solver *s, double *u, const double *f);
 
 /* Residual r = f - det(D^2_h u) at interior nodes (r = 0 on the Dirichlet

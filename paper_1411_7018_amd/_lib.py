@@ -32,7 +32,8 @@ class ma_params(ctypes.Structure):
                 ("max_cycles", ctypes.c_int), ("tol", ctypes.c_double),
                 ("init_tol", ctypes.c_double), ("init_max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("profile", ctypes.c_int),
-                ("tile_config", ctypes.c_int), ("zchunk", ctypes.c_int)]
+                ("tile_config", ctypes.c_int), ("zchunk", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class ma_report(ctypes.Structure):

@@ -1,8 +1,11 @@
-// Batched solves and the resident batch used for continuous serving.
+// Batched solves and the resident batch used for continuous serving.  Both
+// drive many solves through one Engine: every level phase of every tick is
+// one launch over all active solves (the engine's device tables), and each
+// solve follows the same phase machine as ma_solve, so its arithmetic and
+// its stopping decisions do not depend on its co-tenants.
+#include "ma_engine.h"
 #include "ma_runtime.h"
 
-#include <chrono>
-#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -10,24 +13,38 @@
 using namespace mafas;
 
 struct ma_batch {
-    struct Slot {
-        bool active = false;
-        ma_solver *s = nullptr;
-        double *u = nullptr;
-        const double *f = nullptr;
-        double tol = 0.0;
-        ma_report rep{};
-        std::chrono::steady_clock::time_point t0;
-    };
     hipStream_t stream = nullptr;
-    std::vector<Slot> slots;
+    Engine eng;
+    std::vector<SolveRef> refs;
+    std::vector<SolveState> st;
+    std::vector<char> used;
     std::string err;
-    ma_status fail(ma_status st, const std::string &m)
+    ma_status fail(ma_status s, const std::string &m)
     {
         err = m;
-        return st;
+        return s;
+    }
+    bool any() const
+    {
+        for (char c : used)
+            if (c)
+                return true;
+        return false;
     }
 };
+
+namespace {
+
+void start_state(SolveState &st, const ma_solver *s, double tol, unsigned flags)
+{
+    st = SolveState();
+    std::memset(&st.rep, 0, sizeof(st.rep));
+    st.tol = tol > 0.0 ? tol : s->p.tol;
+    st.phase = (flags & MA_INIT_POISSON) ? SolveState::INIT0 : SolveState::MAIN0;
+    st.t0 = now_seconds();
+}
+
+} // namespace
 
 extern "C" {
 
@@ -36,25 +53,69 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
 {
     if (count < 0 || (count > 0 && (!solvers || !u || !f)))
         return MA_ERR_ARG;
-    ma_status first = MA_OK;
-    for (int i = 0; i < count; ++i) {
-        if (!solvers[i])
+    for (int i = 0; i < count; ++i)
+        if (!solvers[i] || !u[i] || !f[i])
             return MA_ERR_ARG;
-        ma_report local;
-        const ma_status st = ma_solve(solvers[i], u[i], f[i], tol, flags, reps ? &reps[i] : &local);
-        if (st != MA_OK && first == MA_OK)
-            first = st;
+    ma_status first = MA_OK;
+    for (int base = 0; base < count; base += kMaxGrids) {
+        const int m = std::min(kMaxGrids, count - base);
+        Engine eng;
+        std::vector<SolveRef> refs(m);
+        for (int i = 0; i < m; ++i) {
+            refs[i].s = solvers[base + i];
+            refs[i].u = u[base + i];
+            refs[i].f = f[base + i];
+        }
+        ma_solver *s0 = solvers[base];
+        if (eng.set(refs, s0->stream, s0->p.graphs != 0, false) != MA_OK)
+            return s0->fail(MA_ERR_ARG, eng.error());
+        std::vector<SolveState> st(m);
+        std::vector<SolveState *> ptr(m);
+        for (int i = 0; i < m; ++i) {
+            start_state(st[i], refs[i].s, tol, flags);
+            ptr[i] = &st[i];
+        }
+        if (eng.reset_counters(-1) != MA_OK)
+            return s0->fail(MA_ERR_DEVICE, eng.error());
+        for (;;) {
+            bool live = false;
+            for (const SolveState &x : st)
+                live |= x.phase != SolveState::DONE;
+            if (!live)
+                break;
+            if (drive_step(eng, ptr) != MA_OK)
+                return s0->fail(MA_ERR_DEVICE, eng.error());
+        }
+        std::vector<unsigned long long> nc, fb;
+        if (eng.read_counters(nc, fb) != MA_OK)
+            return s0->fail(MA_ERR_DEVICE, eng.error());
+        const double t1 = now_seconds();
+        for (int i = 0; i < m; ++i) {
+            SolveState &x = st[i];
+            x.rep.nonconvex = (long long)nc[i];
+            x.rep.fp64_fallbacks = (long long)fb[i];
+            x.rep.seconds = t1 - x.t0;
+            if (reps)
+                reps[base + i] = x.rep;
+            if (x.status != MA_OK) {
+                refs[i].s->err = x.err;
+                if (first == MA_OK)
+                    first = x.status;
+            }
+        }
     }
     return first;
 }
 
 ma_status ma_batch_create(int max_solves, void *hip_stream, ma_batch **out)
 {
-    if (!out || max_solves < 1)
+    if (!out || max_solves < 1 || max_solves > kMaxGrids)
         return MA_ERR_ARG;
     ma_batch *b = new ma_batch();
     b->stream = static_cast<hipStream_t>(hip_stream);
-    b->slots.resize(max_solves);
+    b->refs.resize(max_solves);
+    b->st.resize(max_solves);
+    b->used.assign(max_solves, 0);
     *out = b;
     return MA_OK;
 }
@@ -69,36 +130,30 @@ ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, do
     if (!b || !s || !u || !f || !slot_out)
         return MA_ERR_ARG;
     int slot = -1;
-    for (size_t i = 0; i < b->slots.size(); ++i)
-        if (!b->slots[i].active) {
+    for (size_t i = 0; i < b->used.size(); ++i)
+        if (!b->used[i]) {
             slot = int(i);
             break;
         }
     if (slot < 0)
         return b->fail(MA_ERR_ARG, "no free slot");
-    ma_batch::Slot &sl = b->slots[slot];
-    sl = ma_batch::Slot();
-    sl.s = s;
-    sl.u = u;
-    sl.f = f;
-    sl.tol = tol > 0.0 ? tol : s->p.tol;
-    sl.t0 = std::chrono::steady_clock::now();
-    s->stream = b->stream;
-    s->stats = Stats();
-    ma_report &r = sl.rep;
-    std::memset(&r, 0, sizeof(r));
-    ma_status st = launch_fill_u64(b->stream, 1, 0ull, s->dcount) == hipSuccess ? MA_OK
-                                                                                  : MA_ERR_DEVICE;
-    if (st == MA_OK && (flags & MA_INIT_POISSON))
-        st = s->poisson_init(u, f, &r.init_cycles);
-    if (st == MA_OK) {
-        s->bind_finest(u, f);
-        st = s->norm(OP_MA, u, f, &r.res0);
+    for (size_t i = 0; i < b->used.size(); ++i)
+        if (b->used[i] && b->refs[i].s == s)
+            return b->fail(MA_ERR_ARG, "this solver already holds a slot");
+    b->refs[slot].s = s;
+    b->refs[slot].u = u;
+    b->refs[slot].f = f;
+    const ma_status st = b->eng.set(b->refs, b->stream, s->p.graphs != 0, false);
+    if (st != MA_OK) {
+        b->refs[slot] = SolveRef();
+        if (b->any())
+            (void)b->eng.set(b->refs, b->stream, true, false);
+        return b->fail(st, b->eng.error());
     }
-    if (st != MA_OK)
-        return b->fail(st, s->err);
-    r.res = r.res0;
-    sl.active = true;
+    b->used[slot] = 1;
+    start_state(b->st[slot], s, tol, flags);
+    if (b->eng.reset_counters(slot) != MA_OK)
+        return b->fail(MA_ERR_DEVICE, b->eng.error());
     *slot_out = slot;
     return MA_OK;
 }
@@ -107,62 +162,64 @@ ma_status ma_batch_tick(ma_batch *b, int *done_out)
 {
     if (!b)
         return MA_ERR_ARG;
-    ma_status first = MA_OK;
-    for (size_t i = 0; i < b->slots.size(); ++i) {
-        ma_batch::Slot &sl = b->slots[i];
-        if (done_out)
+    const int S = int(b->used.size());
+    if (done_out)
+        for (int i = 0; i < S; ++i)
             done_out[i] = 0;
-        if (!sl.active || sl.rep.converged)
-            continue;
-        ma_solver *s = sl.s;
-        ma_report &r = sl.rep;
-        ma_status st = MA_OK;
-        if (r.res0 == 0.0) {
-            r.converged = 1;
-        } else {
-            s->bind_finest(sl.u, sl.f);
-            st = s->vcycle(0, OP_MA);
-            if (st == MA_OK)
-                st = s->norm(OP_MA, sl.u, sl.f, &r.res);
-            if (st == MA_OK) {
-                if (r.cycles < 64)
-                    r.history[r.cycles] = r.res;
-                r.cycles += 1;
-                r.rel_res = r.res / r.res0;
-                if (!std::isfinite(r.res))
-                    st = MA_ERR_NONFINITE;
-                else if (r.res <= sl.tol * r.res0)
-                    r.converged = 1;
-                else if (r.cycles >= s->p.max_cycles)
-                    st = MA_ERR_NOT_CONVERGED;
-            }
+    std::vector<SolveState *> ptr(S, nullptr);
+    std::vector<char> was_live(S, 0);
+    bool live = false;
+    for (int i = 0; i < S; ++i)
+        if (b->used[i] && b->st[i].phase != SolveState::DONE) {
+            ptr[i] = &b->st[i];
+            was_live[i] = 1;
+            live = true;
         }
-        r.point_updates = s->stats.updates;
-        r.alg_bytes = s->stats.bytes;
-        r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sl.t0).count();
-        if (st != MA_OK && first == MA_OK) {
-            first = st;
-            b->err = s->err;
+    if (!live)
+        return MA_OK;
+    if (drive_step(b->eng, ptr) != MA_OK)
+        return b->fail(MA_ERR_DEVICE, b->eng.error());
+    bool any_done = false;
+    for (int i = 0; i < S; ++i)
+        any_done |= was_live[i] && b->st[i].phase == SolveState::DONE;
+    if (!any_done)
+        return MA_OK;
+    std::vector<unsigned long long> nc, fb;
+    if (b->eng.read_counters(nc, fb) != MA_OK)
+        return b->fail(MA_ERR_DEVICE, b->eng.error());
+    const double t1 = now_seconds();
+    for (int i = 0; i < S; ++i)
+        if (was_live[i] && b->st[i].phase == SolveState::DONE) {
+            SolveState &x = b->st[i];
+            x.rep.nonconvex = (long long)nc[i];
+            x.rep.fp64_fallbacks = (long long)fb[i];
+            x.rep.seconds = t1 - x.t0;
+            if (done_out)
+                done_out[i] = x.status == MA_OK ? 1 : 2;
         }
-        if (done_out && (r.converged || st != MA_OK))
-            done_out[i] = st == MA_OK ? 1 : 2;
-    }
-    return first;
+    return MA_OK;
 }
 
 ma_status ma_batch_report(const ma_batch *b, int slot, ma_report *rep)
 {
-    if (!b || !rep || slot < 0 || slot >= int(b->slots.size()) || !b->slots[slot].active)
+    if (!b || !rep || slot < 0 || slot >= int(b->used.size()) || !b->used[slot])
         return MA_ERR_ARG;
-    *rep = b->slots[slot].rep;
+    *rep = b->st[slot].rep;
     return MA_OK;
 }
 
 ma_status ma_batch_remove(ma_batch *b, int slot)
 {
-    if (!b || slot < 0 || slot >= int(b->slots.size()) || !b->slots[slot].active)
+    if (!b || slot < 0 || slot >= int(b->used.size()) || !b->used[slot])
         return MA_ERR_ARG;
-    b->slots[slot] = ma_batch::Slot();
+    b->used[slot] = 0;
+    b->refs[slot] = SolveRef();
+    b->st[slot] = SolveState();
+    if (b->any()) {
+        const ma_status st = b->eng.set(b->refs, b->stream, true, false);
+        if (st != MA_OK)
+            return b->fail(st, b->eng.error());
+    }
     return MA_OK;
 }
 

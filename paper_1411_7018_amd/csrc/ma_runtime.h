@@ -24,13 +24,15 @@
 
 namespace mafas {
 
+class Engine;
+
 struct Level {
     int n = 0;
-    double *u = nullptr;   // iterate (level 0: the caller's array)
-    double *b = nullptr;   // right-hand side (level 0: the caller's f or R)
+    double *u = nullptr;   // iterate (coarse levels; level 0 is the caller's array)
+    double *b = nullptr;   // right-hand side (coarse levels)
     double *w = nullptr;   // injected fine approximation (coarse levels)
     double *r = nullptr;   // residual
-    double *t = nullptr;   // out-of-place sweep target
+    double *t = nullptr;   // out-of-place target of the fused sweep
 };
 
 // FP32 inner hierarchy of the mixed-precision form (one per level).
@@ -40,15 +42,7 @@ struct MixedLevel {
     float *b = nullptr;    // right-hand side of T(delta) = b
     float *w = nullptr;    // injected delta
     float *r = nullptr;    // residual of the inner problem
-    float *t = nullptr;    // out-of-place sweep target
     double *U = nullptr;   // injected FP64 approximation (coarse levels)
-};
-
-struct Stats {
-    double updates = 0.0;  // nonlinear GS point updates
-    double bytes = 0.0;    // algorithmic bytes of the kernels launched
-    int smooth_launches = 0;       // finest-level smoother launches (profile)
-    double smooth_bytes = 0.0;     // their algorithmic bytes
 };
 
 size_t hierarchy_bytes(const ma_params *p);
@@ -58,6 +52,8 @@ hipError_t launch_fill(hipStream_t st, size_t count, double v, double *dst);
 hipError_t launch_fill_u64(hipStream_t st, size_t count, unsigned long long v,
                            unsigned long long *dst);
 
+double now_seconds();
+
 } // namespace mafas
 
 struct ma_solver {
@@ -65,44 +61,51 @@ struct ma_solver {
     hipStream_t stream = nullptr;
     std::vector<mafas::Level> lv;
     double *R = nullptr;                  // Poisson right-hand side, finest level
-    double *partials = nullptr;
-    size_t npartials = 0;
+    double *partials = nullptr;           // norm partials of the single-grid kernels
     double *dsum = nullptr;
-    unsigned long long *dcount = nullptr; // non-certified update counter
-    unsigned long long *dfallback = nullptr;
+    unsigned long long *dcount = nullptr; // counter of the single-grid kernels
     double *hpin = nullptr;               // pinned host scalars
     unsigned long long *hpin_u64 = nullptr;
     std::vector<double *> owned;
-    std::string err;
-    mafas::Stats stats;
-    std::vector<hipEvent_t> ev_pool;      // profile: start/stop pairs
-    size_t ev_used = 0;
-
-    // mixed precision
-    std::vector<mafas::MixedLevel> mx;
-    double *r64 = nullptr;                // finest FP64 residual f - S(u)
     std::vector<void *> mixed_owned;
+    std::vector<mafas::MixedLevel> mx;
+    std::string err;
+    mafas::Engine *eng = nullptr;         // batch-of-one engine of ma_solve / ma_vcycle
 
     ~ma_solver();
     ma_status fail(ma_status st, const std::string &msg);
     ma_status alloc(double **q, size_t count);
     ma_status allocate();
-    void bind_finest(double *u, const double *f);
     bool use_fused(int l) const;
     int rmode() const;
+    // single-grid kernels behind the component entry points
     ma_status smooth(int l, double *u, const double *F, int count, int op);
-    ma_status vcycle(int l, int op);
     ma_status finish_norm(int n, double *l2);
-    ma_status norm(int op, const double *u, const double *F, double *l2);
-    ma_status poisson_init(double *u, const double *f, int *cycles);
-    ma_status read_nonconvex(long long *out);
-    ma_status prof_mark(hipEvent_t *ev);
-    ma_status prof_collect(double *seconds);
-    ma_status solve(double *u, const double *f, double tol, unsigned flags, ma_report *r);
-    ma_status solve_fp64(double *u, const double *f, double tol, ma_report *r);
-
-    // mixed precision (ma_mixed.hip)
+    ma_status own_engine(mafas::Engine **out, double *u, const double *f);
     ma_status mixed_allocate();
     void mixed_release();
-    ma_status solve_mixed(double *u, const double *f, double tol, ma_report *r);
 };
+
+namespace mafas {
+
+// Progress of one solve driven tick by tick inside an Engine.
+struct SolveState {
+    enum Phase { INIT0, INIT, MAIN0, MAIN, DONE };
+    Phase phase = MAIN0;
+    double tol = 1e-8;
+    double lin0 = 0.0;      // linear residual of the Poisson guess's start
+    ma_status status = MA_OK;
+    std::string err;
+    ma_report rep{};
+    double t0 = 0.0;        // start time (seconds)
+};
+
+// One scheduling step over the engine's slots: the entry residuals of solves
+// starting a phase, then one tick of every solve that is cycling (Poisson
+// guess, FAS V-cycle or mixed correction).  states[i] may be null (empty
+// slot).  Per-solve outcomes land in the states; the return value reports
+// engine failures only.
+// init_only: stop after the Poisson phases.
+ma_status drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only = false);
+
+} // namespace mafas

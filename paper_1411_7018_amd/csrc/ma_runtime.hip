@@ -1,7 +1,10 @@
-// Host runtime behind the C ABI of include/ma.h: hierarchy allocation, the
-// FAS V-cycle driver (Algorithm 1), the stopping rule of Section 4, the
-// Poisson initial guess, and the resident batch used for serving.
+// Host runtime behind the C ABI of include/ma.h: parameter checks, hierarchy
+// allocation, the component entry points (single-grid kernels) and the
+// solve driver.  Full solves run through the batched engine (a single solve
+// is a batch of one), following Algorithm 1 repeated under the stopping rule
+// of Section 4 after the Poisson initial guess.
 #include "ma.h"
+#include "ma_engine.h"
 #include "ma_internal.h"
 #include "ma_runtime.h"
 
@@ -23,16 +26,12 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "params is NULL";
         return false;
     }
-    if (p->n < 2) {
-        why = "n must be >= 2";
+    if (p->n < 2 || p->n > 2048) {
+        why = "n must satisfy 2 <= n <= 2048";
         return false;
     }
-    if (p->n > 2048) {
-        why = "n must be <= 2048";
-        return false;
-    }
-    if (p->nu1 < 0 || p->nu2 < 0 || p->nu0 < 1 || p->nu1 > 64 || p->nu2 > 64 || p->nu0 > 64) {
-        why = "smoothing counts must satisfy 0 <= nu1, nu2 <= 64 and 1 <= nu0 <= 64";
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu0 < 1 || p->nu1 > 16 || p->nu2 > 16 || p->nu0 > 16) {
+        why = "smoothing counts must satisfy 0 <= nu1, nu2 <= 16 and 1 <= nu0 <= 16";
         return false;
     }
     if (p->order != MA_COLOR4 && p->order != MA_COLOR8) {
@@ -52,11 +51,16 @@ bool valid_params(const ma_params *p, std::string &why)
         return false;
     }
     if (p->tile_config < 0 || p->tile_config > fused_num_configs() || p->zchunk < 0) {
-        why = "tile_config must be 0..fused_num_configs() and zchunk >= 0";
+        why = "tile_config must be in 0..6 and zchunk >= 0";
         return false;
     }
-    if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1) {
-        why = "cycle counts must be >= 0 (inner_cycles >= 1)";
+    if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1 ||
+        p->inner_cycles > 16) {
+        why = "cycle counts must be >= 0 and 1 <= inner_cycles <= 16";
+        return false;
+    }
+    if (p->graphs != 0 && p->graphs != 1) {
+        why = "graphs must be 0 or 1";
         return false;
     }
     if (!std::isfinite(p->tol) || !std::isfinite(p->init_tol)) {
@@ -68,12 +72,18 @@ bool valid_params(const ma_params *p, std::string &why)
 
 } // namespace
 
+double mafas::now_seconds()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 // ---------------------------------------------------------------------------
-// Hierarchy layout (all FP64, (n_l+1)^3 each):
-//   level 0: r (residual), R (Poisson right-hand side), t (sweep target);
-//   level l >= 1: u, b (right-hand side), w (injected approximation), r, t.
-// Plus the residual partial sums (sized for level 0), one device scalar and
-// one device counter.  The MA_MIXED buffers are added by the mixed module.
+// Hierarchy layout (FP64, (n_l+1)^3 each):
+//   level 0: r (residual), R (Poisson right-hand side), t (fused target);
+//   level l >= 1: u, b, w, r, t.
+// Plus the single-grid norm partials, the batch-of-one engine's partials and
+// lists, and the MA_MIXED FP32 hierarchy.
 // ---------------------------------------------------------------------------
 size_t mafas::hierarchy_bytes(const ma_params *p)
 {
@@ -84,7 +94,9 @@ size_t mafas::hierarchy_bytes(const ma_params *p)
         const size_t c = npts(ns[l]) * sizeof(double);
         b += (l == 0) ? 3 * c : 5 * c;
     }
-    b += residual_partials(p->n) * sizeof(double) + 256;
+    b += residual_partials(p->n) * sizeof(double);
+    const size_t rows = size_t((p->n - 1 + 63) / 64) * size_t(p->n - 1) * size_t(p->n - 1);
+    b += rows * sizeof(double) + (64 << 10) + 4096;
     if (p->precision == MA_MIXED)
         b += mixed_bytes(p);
     return b;
@@ -108,6 +120,7 @@ void ma_params_default(ma_params *p, int n)
     p->init_tol = 1e-6;
     p->init_max_cycles = 30;
     p->inner_cycles = 2;
+    p->graphs = 1;
 }
 
 int ma_levels(int n, int *ns, int cap)
@@ -178,9 +191,36 @@ ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigne
         return MA_ERR_ARG;
     if (!u || !f)
         return s->fail(MA_ERR_ARG, "u and f must be device pointers");
-    ma_report local;
-    ma_report *r = rep ? rep : &local;
-    return s->solve(u, f, tol > 0.0 ? tol : s->p.tol, flags, r);
+    Engine *E = nullptr;
+    MA_TRY(s->own_engine(&E, u, f));
+    SolveState st;
+    st.tol = tol > 0.0 ? tol : s->p.tol;
+    st.phase = (flags & MA_INIT_POISSON) ? SolveState::INIT0 : SolveState::MAIN0;
+    st.t0 = now_seconds();
+    std::memset(&st.rep, 0, sizeof(st.rep));
+    if (E->reset_counters(0) != MA_OK)
+        return s->fail(MA_ERR_DEVICE, E->error());
+    std::vector<SolveState *> states{&st};
+    while (st.phase != SolveState::DONE) {
+        if (drive_step(*E, states) != MA_OK)
+            return s->fail(MA_ERR_DEVICE, E->error());
+    }
+    std::vector<unsigned long long> nc, fb;
+    if (E->read_counters(nc, fb) == MA_OK) {
+        st.rep.nonconvex = (long long)nc[0];
+        st.rep.fp64_fallbacks = (long long)fb[0];
+    }
+    if (s->p.profile) {
+        int launches = 0;
+        E->take_profile(&st.rep.smooth_seconds, &launches, &st.rep.smooth_bytes);
+        st.rep.smooth_launches = launches;
+    }
+    st.rep.seconds = now_seconds() - st.t0;
+    if (rep)
+        *rep = st.rep;
+    if (st.status != MA_OK)
+        return s->fail(st.status, st.err);
+    return MA_OK;
 }
 
 ma_status ma_vcycle(ma_solver *s, double *u, const double *f)
@@ -191,8 +231,12 @@ ma_status ma_vcycle(ma_solver *s, double *u, const double *f)
         return s->fail(MA_ERR_ARG, "u and f must be device pointers");
     if (s->p.precision == MA_MIXED)
         return s->fail(MA_ERR_ARG, "ma_vcycle runs FP64 cycles; MA_MIXED solvers use ma_solve");
-    s->bind_finest(u, f);
-    return s->vcycle(0, OP_MA);
+    Engine *E = nullptr;
+    MA_TRY(s->own_engine(&E, u, f));
+    std::vector<double> norms;
+    if (E->tick(Engine::MODE_MA, std::vector<char>{1}, norms) != MA_OK)
+        return s->fail(MA_ERR_DEVICE, E->error());
+    return MA_OK;
 }
 
 ma_status ma_residual(ma_solver *s, const double *u, const double *f, double *r_or_null,
@@ -202,15 +246,12 @@ ma_status ma_residual(ma_solver *s, const double *u, const double *f, double *r_
         return MA_ERR_ARG;
     if (!u || !f)
         return s->fail(MA_ERR_ARG, "u and f must be device pointers");
-    if (r_or_null) {
+    if (r_or_null)
         MA_HIP(s, launch_fill(s->stream, npts(s->p.n), 0.0, r_or_null));
-    }
     MA_HIP(s, launch_residual(s->stream, OP_MA, s->p.n, u, f, r_or_null, s->partials));
     if (l2_host) {
         double l2;
-        const ma_status st = s->finish_norm(s->p.n, &l2);
-        if (st != MA_OK)
-            return st;
+        MA_TRY(s->finish_norm(s->p.n, &l2));
         *l2_host = l2;
     }
     return MA_OK;
@@ -225,9 +266,8 @@ ma_status ma_sweep(ma_solver *s, double *u, const double *f, int count, long lon
     MA_HIP(s, launch_fill_u64(s->stream, 1, 0ull, s->dcount));
     MA_TRY(s->smooth(0, u, f, count, OP_MA));
     if (nonconvex_host) {
-        unsigned long long c = 0;
-        MA_HIP(s, hipMemcpyAsync(s->hpin_u64, s->dcount, sizeof(c), hipMemcpyDeviceToHost,
-                                 s->stream));
+        MA_HIP(s, hipMemcpyAsync(s->hpin_u64, s->dcount, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, s->stream));
         MA_HIP(s, hipStreamSynchronize(s->stream));
         *nonconvex_host = (long long)s->hpin_u64[0];
     }
@@ -244,8 +284,8 @@ ma_status ma_restrict(ma_solver *s, const double *u, const double *f, double *w_
         return s->fail(MA_ERR_ARG, "n must be even and >= 4 for a coarser level");
     const int n = s->p.n;
     MA_HIP(s, launch_residual(s->stream, OP_MA, n, u, f, s->lv[0].r, s->partials));
-    MA_HIP(s, launch_restrict(s->stream, OP_MA, s->rmode(), n, u, s->lv[0].r, w_c,
-                              s->lv[1].u, b_c));
+    MA_HIP(s, launch_restrict(s->stream, OP_MA, s->rmode(), n, u, s->lv[0].r, w_c, s->lv[1].u,
+                              b_c));
     return MA_OK;
 }
 
@@ -267,10 +307,22 @@ ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_
         return MA_ERR_ARG;
     if (!u || !f)
         return s->fail(MA_ERR_ARG, "u and f must be device pointers");
-    int c = 0;
-    MA_TRY(s->poisson_init(u, f, &c));
+    Engine *E = nullptr;
+    MA_TRY(s->own_engine(&E, u, f));
+    SolveState st;
+    st.phase = SolveState::INIT0;
+    std::memset(&st.rep, 0, sizeof(st.rep));
+    std::vector<SolveState *> states{&st};
+    // drive the Poisson phases only: stop once the solve would start its
+    // main phase (the residual of the guess is not needed here)
+    while (st.phase == SolveState::INIT0 || st.phase == SolveState::INIT) {
+        if (drive_step(*E, states, true) != MA_OK)
+            return s->fail(MA_ERR_DEVICE, E->error());
+    }
+    if (st.status != MA_OK)
+        return s->fail(st.status, st.err);
     if (cycles_host)
-        *cycles_host = c;
+        *cycles_host = st.rep.init_cycles;
     return MA_OK;
 }
 
@@ -281,8 +333,7 @@ ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_
 // ---------------------------------------------------------------------------
 ma_solver::~ma_solver()
 {
-    for (hipEvent_t e : ev_pool)
-        (void)hipEventDestroy(e);
+    delete eng;
     for (double *q : owned)
         (void)hipFree(q);
     if (hpin)
@@ -338,8 +389,7 @@ ma_status ma_solver::allocate()
             MA_TRY(alloc(&v.t, c));
         }
     }
-    npartials = residual_partials(p.n);
-    MA_TRY(alloc(&partials, npartials));
+    MA_TRY(alloc(&partials, residual_partials(p.n)));
     MA_TRY(alloc(&dsum, 4));
     {
         const hipError_t e = hipMalloc(reinterpret_cast<void **>(&dcount), 64);
@@ -359,12 +409,6 @@ ma_status ma_solver::allocate()
     return MA_OK;
 }
 
-void ma_solver::bind_finest(double *u, const double *f)
-{
-    lv[0].u = u;
-    lv[0].b = const_cast<double *>(f);
-}
-
 bool ma_solver::use_fused(int l) const
 {
     if (p.order != MA_COLOR4 || p.smoother == MA_SMOOTHER_COLOR)
@@ -374,42 +418,12 @@ bool ma_solver::use_fused(int l) const
     return fused_supported(lv[l].n);
 }
 
-// Profiling: events are recorded in pairs around finest-level smoothing and
-// read back (elapsed time summed) when the solve synchronises anyway.
-ma_status ma_solver::prof_mark(hipEvent_t *ev)
-{
-    if (ev_used == ev_pool.size()) {
-        hipEvent_t e;
-        MA_HIP(this, hipEventCreate(&e));
-        ev_pool.push_back(e);
-    }
-    *ev = ev_pool[ev_used++];
-    MA_HIP(this, hipEventRecord(*ev, stream));
-    return MA_OK;
-}
+int ma_solver::rmode() const { return p.restriction == MA_RESTRICT_HALF ? 1 : 0; }
 
-ma_status ma_solver::prof_collect(double *seconds)
-{
-    double t = 0.0;
-    for (size_t q = 0; q + 1 < ev_used; q += 2) {
-        float ms = 0.f;
-        MA_HIP(this, hipEventSynchronize(ev_pool[q + 1]));
-        MA_HIP(this, hipEventElapsedTime(&ms, ev_pool[q], ev_pool[q + 1]));
-        t += 1e-3 * double(ms);
-    }
-    ev_used = 0;
-    *seconds = t;
-    return MA_OK;
-}
-
-// count sweeps of op on u (level l) with right-hand side F; the result is in u.
+// count single-grid sweeps of op on level l; the result ends in u.
 ma_status ma_solver::smooth(int l, double *u, const double *F, int count, int op)
 {
     const int n = lv[l].n;
-    const bool prof = p.profile && l == 0 && op == OP_MA && count > 0;
-    hipEvent_t e0, e1;
-    if (prof)
-        MA_TRY(prof_mark(&e0));
     int done = 0;
     if (use_fused(l) && count >= 2) {
         double *t = lv[l].t;
@@ -421,43 +435,12 @@ ma_status ma_solver::smooth(int l, double *u, const double *F, int count, int op
                                             p.zchunk));
         }
     }
-    const int fused_launches = done;
     for (; done < count; ++done)
         MA_HIP(this, launch_sweep_color(stream, op, p.order, n, u, F, dcount));
-    if (op == OP_MA) {
-        stats.updates += double(count) * interior(n);
-        stats.bytes += double(count) * 24.0 * interior(n);
-    }
-    if (prof) {
-        MA_TRY(prof_mark(&e1));
-        stats.smooth_launches += fused_launches + (count - fused_launches) * (p.order == 1 ? 8 : 4);
-        stats.smooth_bytes += double(count) * 24.0 * interior(n);
-    }
     return MA_OK;
 }
 
-int ma_solver::rmode() const { return p.restriction == MA_RESTRICT_HALF ? 1 : 0; }
-
-// Algorithm 1 on level l: u = lv[l].u, right-hand side lv[l].b.
-ma_status ma_solver::vcycle(int l, int op)
-{
-    Level &v = lv[l];
-    const int L = int(lv.size());
-    if (l == L - 1)
-        return smooth(l, v.u, v.b, p.nu0, op);
-    MA_TRY(smooth(l, v.u, v.b, p.nu1, op));
-    Level &c = lv[l + 1];
-    MA_HIP(this, launch_residual(stream, op, v.n, v.u, v.b, v.r, partials));
-    MA_HIP(this, launch_restrict(stream, op, rmode(), v.n, v.u, v.r, c.w, c.u, c.b));
-    const double fine = interior(v.n), coarse = double(npts(c.n));
-    stats.bytes += 24.0 * fine + 8.0 * fine + 8.0 * coarse + 24.0 * coarse;
-    MA_TRY(vcycle(l + 1, op));
-    MA_HIP(this, launch_prolong(stream, v.n, v.u, c.u, c.w));
-    stats.bytes += 16.0 * fine + 16.0 * coarse;
-    return smooth(l, v.u, v.b, p.nu2, op);
-}
-
-// partials of level n -> host l2 = sqrt(h^3 sum r^2) (synchronises).
+// partials of an n grid -> host l2 = sqrt(h^3 sum r^2) (synchronises).
 ma_status ma_solver::finish_norm(int n, double *l2)
 {
     MA_HIP(this, launch_reduce(stream, partials, residual_partials(n), dsum));
@@ -468,100 +451,138 @@ ma_status ma_solver::finish_norm(int n, double *l2)
     return MA_OK;
 }
 
-ma_status ma_solver::norm(int op, const double *u, const double *F, double *l2)
+ma_status ma_solver::own_engine(Engine **out, double *u, const double *f)
 {
-    MA_HIP(this, launch_residual(stream, op, p.n, u, F, nullptr, partials));
-    stats.bytes += 16.0 * interior(p.n);
-    return finish_norm(p.n, l2);
-}
-
-ma_status ma_solver::poisson_init(double *u, const double *f, int *cycles)
-{
-    *cycles = 0;
-    MA_HIP(this, launch_poisson_rhs(stream, p.n, f, R));
-    bind_finest(u, R);
-    double r0, r;
-    MA_TRY(norm(OP_LAP, u, R, &r0));
-    if (!std::isfinite(r0))
-        return fail(MA_ERR_NONFINITE, "Poisson initial residual is not finite");
-    if (r0 == 0.0)
-        return MA_OK;
-    while (*cycles < p.init_max_cycles) {
-        MA_TRY(vcycle(0, OP_LAP));
-        ++*cycles;
-        MA_TRY(norm(OP_LAP, u, R, &r));
-        if (!std::isfinite(r))
-            return fail(MA_ERR_NONFINITE, "Poisson residual is not finite");
-        if (r <= p.init_tol * r0)
-            break;
-    }
+    if (!eng)
+        eng = new Engine();
+    std::vector<SolveRef> refs(1);
+    refs[0].s = this;
+    refs[0].u = u;
+    refs[0].f = f;
+    if (eng->set(refs, stream, p.graphs != 0, p.profile != 0) != MA_OK)
+        return fail(MA_ERR_DEVICE, eng->error());
+    *out = eng;
     return MA_OK;
 }
 
-ma_status ma_solver::read_nonconvex(long long *out)
+// ---------------------------------------------------------------------------
+// Per-solve phase machine shared by ma_solve, ma_solve_batch and ma_batch.
+// ---------------------------------------------------------------------------
+ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only)
 {
-    MA_HIP(this, hipMemcpyAsync(hpin_u64, dcount, sizeof(unsigned long long),
-                                hipMemcpyDeviceToHost, stream));
-    MA_HIP(this, hipStreamSynchronize(stream));
-    *out = (long long)hpin_u64[0];
-    return MA_OK;
-}
-
-ma_status ma_solver::solve(double *u, const double *f, double tol, unsigned flags, ma_report *r)
-{
-    const auto t0 = std::chrono::steady_clock::now();
-    std::memset(r, 0, sizeof(*r));
-    stats = Stats();
-    ev_used = 0;
-    MA_HIP(this, launch_fill_u64(stream, 1, 0ull, dcount));
-    if (flags & MA_INIT_POISSON)
-        MA_TRY(poisson_init(u, f, &r->init_cycles));
-    ma_status st;
-    if (p.precision == MA_MIXED)
-        st = solve_mixed(u, f, tol, r);
-    else
-        st = solve_fp64(u, f, tol, r);
-    long long nc = 0;
-    if (read_nonconvex(&nc) == MA_OK)
-        r->nonconvex += nc;
-    r->point_updates = stats.updates;
-    r->alg_bytes = stats.bytes;
-    if (p.profile) {
-        double t = 0.0;
-        if (prof_collect(&t) == MA_OK) {
-            r->smooth_seconds = t;
-            r->smooth_launches = stats.smooth_launches;
-            r->smooth_bytes = stats.smooth_bytes;
+    const int S = int(states.size());
+    std::vector<char> act(S, 0);
+    std::vector<double> nrm;
+    auto finish = [&](SolveState *st, ma_status s, const char *why) {
+        st->status = s;
+        if (s != MA_OK)
+            st->err = why;
+        st->phase = SolveState::DONE;
+    };
+    auto select = [&](SolveState::Phase ph) {
+        bool any = false;
+        for (int i = 0; i < S; ++i) {
+            act[i] = states[i] && states[i]->phase == ph;
+            any |= act[i] != 0;
         }
-    }
-    r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return st;
-}
+        return any;
+    };
+    const Engine::Mode main_mode = eng.mixed() ? Engine::MODE_MIXED : Engine::MODE_MA;
 
-ma_status ma_solver::solve_fp64(double *u, const double *f, double tol, ma_report *r)
-{
-    bind_finest(u, f);
-    MA_TRY(norm(OP_MA, u, f, &r->res0));
-    r->res = r->res0;
-    if (!std::isfinite(r->res0))
-        return fail(MA_ERR_NONFINITE, "initial residual is not finite");
-    if (r->res0 == 0.0) {
-        r->converged = 1;
+    // 1. Poisson right-hand sides and the linear residuals of the start
+    if (select(SolveState::INIT0)) {
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                const SolveRef &r = eng.ref(i);
+                if (launch_poisson_rhs(eng.user(), r.s->p.n, r.f, r.s->R) != hipSuccess)
+                    return MA_ERR_DEVICE;
+            }
+        MA_TRY(eng.norms_only(Engine::MODE_LAP, act, nrm));
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                SolveState *st = states[i];
+                st->lin0 = nrm[i];
+                if (!std::isfinite(nrm[i]))
+                    finish(st, MA_ERR_NONFINITE, "Poisson initial residual is not finite");
+                else if (nrm[i] == 0.0 || eng.ref(i).s->p.init_max_cycles == 0)
+                    st->phase = SolveState::MAIN0;
+                else
+                    st->phase = SolveState::INIT;
+            }
+    }
+    // 2. one linear V-cycle of the Poisson guess
+    if (select(SolveState::INIT)) {
+        MA_TRY(eng.tick(Engine::MODE_LAP, act, nrm));
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                SolveState *st = states[i];
+                const ma_params &p = eng.ref(i).s->p;
+                double up, by;
+                eng.tick_cost(Engine::MODE_LAP, i, &up, &by);
+                st->rep.alg_bytes += by;
+                st->rep.init_cycles += 1;
+                if (!std::isfinite(nrm[i]))
+                    finish(st, MA_ERR_NONFINITE, "Poisson residual is not finite");
+                else if (nrm[i] <= p.init_tol * st->lin0 ||
+                         st->rep.init_cycles >= p.init_max_cycles)
+                    st->phase = SolveState::MAIN0;
+            }
+    }
+    if (init_only)
         return MA_OK;
+    // 3. residual of the initial guess (res0 of the stopping rule)
+    if (select(SolveState::MAIN0)) {
+        MA_TRY(eng.norms_only(main_mode, act, nrm));
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                SolveState *st = states[i];
+                st->rep.res0 = st->rep.res = nrm[i];
+                if (!std::isfinite(nrm[i]))
+                    finish(st, MA_ERR_NONFINITE, "initial residual is not finite");
+                else if (nrm[i] == 0.0) {
+                    st->rep.converged = 1;
+                    finish(st, MA_OK, "");
+                } else if (eng.ref(i).s->p.max_cycles == 0) {
+                    finish(st, MA_ERR_NOT_CONVERGED, "max_cycles is 0");
+                } else {
+                    st->phase = SolveState::MAIN;
+                }
+            }
     }
-    for (int c = 0; c < p.max_cycles; ++c) {
-        MA_TRY(vcycle(0, OP_MA));
-        r->cycles = c + 1;
-        MA_TRY(norm(OP_MA, u, f, &r->res));
-        if (c < 64)
-            r->history[c] = r->res;
-        r->rel_res = r->res / r->res0;
-        if (!std::isfinite(r->res))
-            return fail(MA_ERR_NONFINITE, "residual is not finite");
-        if (r->res <= tol * r->res0) {
-            r->converged = 1;
-            return MA_OK;
-        }
+    // 4. one V-cycle (FP64) or one outer correction (mixed)
+    if (select(SolveState::MAIN)) {
+        MA_TRY(eng.tick(main_mode, act, nrm));
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                SolveState *st = states[i];
+                const ma_params &p = eng.ref(i).s->p;
+                ma_report &r = st->rep;
+                double up, by;
+                eng.tick_cost(main_mode, i, &up, &by);
+                r.point_updates += up;
+                r.alg_bytes += by;
+                int steps;
+                if (main_mode == Engine::MODE_MIXED) {
+                    r.cycles += p.inner_cycles;
+                    r.outer += 1;
+                    steps = r.outer;
+                } else {
+                    r.cycles += 1;
+                    steps = r.cycles;
+                }
+                if (steps - 1 < 64)
+                    r.history[steps - 1] = nrm[i];
+                r.res = nrm[i];
+                r.rel_res = r.res / r.res0;
+                if (!std::isfinite(r.res)) {
+                    finish(st, MA_ERR_NONFINITE, "residual is not finite");
+                } else if (r.res <= st->tol * r.res0) {
+                    r.converged = 1;
+                    finish(st, MA_OK, "");
+                } else if (steps >= p.max_cycles) {
+                    finish(st, MA_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
+                }
+            }
     }
-    return fail(MA_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
+    return MA_OK;
 }

@@ -1,0 +1,145 @@
+"""Batched engine: a solve's result is the same alone, in a batch and in a
+resident (serving) batch that others join and leave; hipGraph replay gives
+the same result as eager launches."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_7018_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def note(*args):
+    print("[case]", *args, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+SPECS = [("quadratic", 16, 1), ("exp_cos", 24, 2), ("example4", 32, 3), ("exp_cos", 33, 4),
+         ("quadratic", 48, 5), ("exp_cos", 64, 6), ("example4", 2, 7), ("exp_cos", 96, 8)]
+
+
+def solo(kind, n, seed, **kw):
+    from paper_1411_7018_amd import Solver
+    p = P.make(kind, n, seed)
+    s = Solver(n, **kw)
+    u = dev(P.initial_guess(p))
+    rep = s.solve(u, dev(p.f))
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_bitwise_equals_solo(precision):
+    from paper_1411_7018_amd import Solver
+    from paper_1411_7018_amd.batch import solve_batch
+    note("batch vs solo", precision)
+    probs = [P.make(k, n, s) for k, n, s in SPECS]
+    solvers = [Solver(p.n, precision=precision) for p in probs]
+    us = [dev(P.initial_guess(p)) for p in probs]
+    fs = [dev(p.f) for p in probs]
+    st, reps = solve_batch(solvers, us, fs)
+    assert st == 0
+    for (k, n, s), u, rep in zip(SPECS, us, reps):
+        want, rs = solo(k, n, s, precision=precision)
+        assert rep["cycles"] == rs["cycles"] and rep["init_cycles"] == rs["init_cycles"]
+        assert np.array_equal(u.cpu().numpy(), want), (k, n)
+        assert rep["res"] == rs["res"]
+
+
+def test_batch_matches_oracle():
+    """Every batched FP64 result equals the oracle's run of the same cycle
+    count (<= 1e-12 relative max-norm)."""
+    from paper_1411_7018_amd import Solver
+    from paper_1411_7018_amd.batch import solve_batch
+    note("batch vs oracle")
+    specs = SPECS[:6]
+    probs = [P.make(k, n, s) for k, n, s in specs]
+    solvers = [Solver(p.n) for p in probs]
+    us = [dev(P.initial_guess(p)) for p in probs]
+    st, reps = solve_batch(solvers, us, [dev(p.f) for p in probs])
+    for p, u, rep in zip(probs, us, reps):
+        want = P.initial_guess(p)
+        oracle.poisson_init(want, p.f, oracle.params())
+        for _ in range(rep["cycles"]):
+            oracle.vcycle(want, p.f, oracle.params())
+        got = u.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager(precision):
+    """hipGraph replays (several solves in a row on one solver, with host
+    work between them) give bitwise the eager-launch result every time."""
+    from paper_1411_7018_amd import Solver
+    note("graph vs eager", precision)
+    p = P.exp_cos(40, seed=9)
+    eager = Solver(40, precision=precision, graphs=0)
+    u0 = dev(P.initial_guess(p))
+    eager.solve(u0, dev(p.f))
+    want = u0.cpu().numpy()
+    g = Solver(40, precision=precision, graphs=1)
+    for rep in range(3):
+        u = dev(P.initial_guess(p))
+        g.solve(u, dev(p.f))
+        torch.cuda.synchronize()
+        assert np.array_equal(u.cpu().numpy(), want), rep
+        _ = np.linalg.norm(want)            # host work between replays
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_batch_join_and_leave(precision):
+    """Continuous batching: solves join while others are cycling, leave when
+    done; each result is bitwise its solo result."""
+    from paper_1411_7018_amd import Solver
+    from paper_1411_7018_amd.batch import ResidentBatch
+    note("resident batch", precision)
+    b = ResidentBatch(8)
+    pending = list(SPECS)
+    live = {}
+    finished = {}
+    tick = 0
+    while pending or live:
+        if pending and (tick % 2 == 0 or not live):
+            k, n, s = pending.pop(0)
+            p = P.make(k, n, s)
+            sv = Solver(n, precision=precision)
+            u = dev(P.initial_guess(p))
+            slot = b.add(sv, u, dev(p.f))
+            live[slot] = ((k, n, s), u)
+        done = b.tick()
+        for slot, code in done.items():
+            assert code == 1
+            spec, u = live.pop(slot)
+            finished[spec] = (u.cpu().numpy(), b.report(slot))
+            b.remove(slot)
+        tick += 1
+        assert tick < 500
+    for spec in SPECS:
+        want, rs = solo(*spec, precision=precision)
+        got, rep = finished[spec]
+        assert rep["cycles"] == rs["cycles"]
+        assert np.array_equal(got, want), spec
+
+
+def test_batch_rejects_mixed_parameters():
+    from paper_1411_7018_amd import Solver
+    from paper_1411_7018_amd._lib import MAError
+    from paper_1411_7018_amd.batch import ResidentBatch
+    b = ResidentBatch(4)
+    p = P.example4(16)
+    b.add(Solver(16), dev(P.initial_guess(p)), dev(p.f))
+    with pytest.raises(MAError):
+        b.add(Solver(16, precision="mixed"), dev(P.initial_guess(p)), dev(p.f))
