@@ -205,13 +205,21 @@ ma_status ma_batch_create(int max_solves, void *hip_stream, ma_batch **out);
 void ma_batch_destroy(ma_batch *b);
 const char *ma_batch_last_error(const ma_batch *b);
 
-/* Join: prepares u (Poisson guess when flags has MA_INIT_POISSON) and
- * computes res0 on the batch's stream.  *slot_out receives the slot id. */
+/* Join: claims a free slot (*slot_out) and resets its counters; no solver
+ * work runs here.  The solve's own phases follow in the next ticks: with
+ * MA_INIT_POISSON its Poisson guess (one linear V-cycle per tick), then its
+ * entry residual res0, then its V-cycles.  All solvers of a batch share
+ * nu1, nu2, nu0, order, restriction, precision and inner_cycles (else
+ * MA_ERR_ARG); a solver holds at most one slot.  The tick replay mode
+ * (graphs) is that of the first solver added to an empty batch.
+ * Errors: MA_ERR_ARG (null argument, no free slot, incompatible solver). */
 ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, double tol,
                        unsigned flags, int *slot_out);
 
 /* One tick over all active slots; done_out[slot] (host, max_solves entries,
- * may be NULL) is set to 1 for slots that converged or failed this tick. */
+ * may be NULL) is set to 1 for slots that converged this tick and to 2 for
+ * slots that stopped with an error (its status: ma_batch_report's fields and
+ * ma_batch_last_error); 0 otherwise.  Synchronises the batch's stream. */
 ma_status ma_batch_tick(ma_batch *b, int *done_out);
 
 /* Report of a slot (valid while it is in the batch). */

@@ -18,6 +18,7 @@ struct ma_batch {
     std::vector<SolveRef> refs;
     std::vector<SolveState> st;
     std::vector<char> used;
+    bool graphs = true;   // tick replay mode, taken from the first solver added
     std::string err;
     ma_status fail(ma_status s, const std::string &m)
     {
@@ -140,14 +141,16 @@ ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, do
     for (size_t i = 0; i < b->used.size(); ++i)
         if (b->used[i] && b->refs[i].s == s)
             return b->fail(MA_ERR_ARG, "this solver already holds a slot");
+    if (!b->any())
+        b->graphs = s->p.graphs != 0;
     b->refs[slot].s = s;
     b->refs[slot].u = u;
     b->refs[slot].f = f;
-    const ma_status st = b->eng.set(b->refs, b->stream, s->p.graphs != 0, false);
+    const ma_status st = b->eng.set(b->refs, b->stream, b->graphs, false);
     if (st != MA_OK) {
         b->refs[slot] = SolveRef();
         if (b->any())
-            (void)b->eng.set(b->refs, b->stream, true, false);
+            (void)b->eng.set(b->refs, b->stream, b->graphs, false);
         return b->fail(st, b->eng.error());
     }
     b->used[slot] = 1;
@@ -216,7 +219,7 @@ ma_status ma_batch_remove(ma_batch *b, int slot)
     b->refs[slot] = SolveRef();
     b->st[slot] = SolveState();
     if (b->any()) {
-        const ma_status st = b->eng.set(b->refs, b->stream, true, false);
+        const ma_status st = b->eng.set(b->refs, b->stream, b->graphs, false);
         if (st != MA_OK)
             return b->fail(st, b->eng.error());
     }

@@ -31,8 +31,8 @@ struct GridItem {
     void *p[6];    // operands, meaning set by the list kind
 };
 
-// Lists are stored packed in one device buffer: the header followed by
-// ngrids descriptors (the g[] bound below is only the maximum).
+// Lists live in one device buffer at a fixed stride of list_bytes(slots):
+// the header followed by ngrids descriptors (g[] below is only the bound).
 struct BatchList {
     int ngrids;
     int total;     // work items over all grids
@@ -149,9 +149,19 @@ class Engine {
     Mode built_mode_ = MODE_MA;
     std::vector<char> built_active_;
     bool built_ = false;
-    hipGraphExec_t gexec_[3] = {nullptr, nullptr, nullptr};
-    int graph_D_[3] = {-1, -1, -1};
-    const char *graph_dl_[3] = {nullptr, nullptr, nullptr};
+    // Captured ticks, one slot per mode; slot mode + 3 is the profiled form:
+    // the tick split into segments at the finest-level sweep boundaries, so
+    // the timing events are recorded on the stream between segment launches.
+    static constexpr int kSlots = 6;
+    std::vector<hipGraphExec_t> gseg_[kSlots];
+    int graph_D_[kSlots] = {-1, -1, -1, -1, -1, -1};
+    const char *graph_dl_[kSlots] = {};
+    size_t graph_stride_[kSlots] = {};   // list stride a graph was captured with
+    size_t graph_nl_[kSlots] = {};       // list count a graph was captured with
+    size_t stride_ = 0;                  // bytes per list: list_bytes(slots)
+    bool seg_capture_ = false;           // prof_mark() cuts the capture
+    std::vector<hipGraph_t> seg_tmp_;
+    ma_status capture(int slot, Mode mode);
 
     std::vector<hipEvent_t> pev_;          // profile event pairs (finest sweeps)
     size_t pev_used_ = 0;

@@ -450,12 +450,15 @@ Engine::~Engine()
 
 void Engine::drop_graphs()
 {
-    for (int m = 0; m < 3; ++m) {
-        if (gexec_[m])
-            (void)hipGraphExecDestroy(gexec_[m]);
-        gexec_[m] = nullptr;
+    for (int m = 0; m < kSlots; ++m) {
+        for (hipGraphExec_t x : gseg_[m])
+            if (x)
+                (void)hipGraphExecDestroy(x);
+        gseg_[m].clear();
         graph_D_[m] = -1;
         graph_dl_[m] = nullptr;
+        graph_stride_[m] = 0;
+        graph_nl_[m] = 0;
     }
 }
 
@@ -489,6 +492,18 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
+    // A captured tick reads the grids' operand pointers from the device lists,
+    // which every rebuild rewrites; what it holds as plain kernel arguments
+    // is the partials buffer and, on the fused path, the grids themselves.
+    // A change of either invalidates the graphs.
+    const bool fused = solves.size() == 1 && p0->smoother == MA_SMOOTHER_FUSED &&
+                       p0->order == MA_COLOR4;
+    bool same = solves.size() == solves_.size();
+    for (size_t i = 0; same && i < solves.size(); ++i)
+        same = solves[i].s == solves_[i].s && solves[i].u == solves_[i].u &&
+               solves[i].f == solves_[i].f;
+    if (fused != fused_ || (fused && !same))
+        drop_graphs();
     solves_ = solves;
     user_ = user;
     graphs_ = graphs;
@@ -500,7 +515,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     rmode_ = p0->restriction == MA_RESTRICT_HALF ? 1 : 0;
     inner_ = p0->inner_cycles;
     mixed_ = p0->precision == MA_MIXED;
-    fused_ = solves.size() == 1 && p0->smoother == MA_SMOOTHER_FUSED && p0->order == MA_COLOR4;
+    fused_ = fused;
     built_ = false;
     if (!stream_) {
         E_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
@@ -521,6 +536,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         }
     if (need > partials_cap_) {
         E_HIP(hipStreamSynchronize(stream_));
+        drop_graphs();
         (void)hipFree(partials_);
         partials_ = nullptr;
         E_HIP(hipMalloc(reinterpret_cast<void **>(&partials_), need * sizeof(double)));
@@ -660,6 +676,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
     hbuf_.clear();
     loff_.clear();
     lng_.clear();
+    stride_ = list_bytes(int(solves_.size()));
     const int S = int(solves_.size());
     auto on = [&](int i) { return solves_[i].s && active[i]; };
     auto levels = [&](int i) { return int(solves_[i].s->lv.size()); };
@@ -697,11 +714,14 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             L.g[L.ngrids++] = G;
         }
         L.total = start;
-        const size_t nb = list_bytes(L.ngrids);
-        loff_.push_back(hbuf_.size());
+        // every list sits at index * stride_, so a list's device address
+        // depends only on its index: graphs captured for one composition
+        // stay valid when solves join or leave (same depth, same slots)
+        const size_t off = loff_.size() * stride_;
+        loff_.push_back(off);
         lng_.push_back(L.ngrids);
-        hbuf_.insert(hbuf_.end(), reinterpret_cast<const char *>(&L),
-                     reinterpret_cast<const char *>(&L) + nb);
+        hbuf_.resize(off + stride_, 0);
+        std::memcpy(hbuf_.data() + off, &L, list_bytes(L.ngrids));
         return int(loff_.size()) - 1;
     };
     const int ksw = std::max(nu1_, nu0_);
@@ -788,6 +808,17 @@ ma_status Engine::upload()
 
 ma_status Engine::prof_mark()
 {
+    if (seg_capture_) {
+        // close the current segment and open the next one
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(stream_, &g);
+        if (g)
+            seg_tmp_.push_back(g);
+        E_HIP(e);
+        E_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+        ++pev_used_;
+        return MA_OK;
+    }
     if (pev_used_ == pev_.size()) {
         hipEvent_t e;
         E_HIP(hipEventCreate(&e));
@@ -888,32 +919,30 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         MA_TRY(rebuild(mode, active));
     E_HIP(hipEventRecord(ev_in_, user_));
     E_HIP(hipStreamWaitEvent(stream_, ev_in_, 0));
-    const int m = int(mode);
-    if (cycle && graphs_ && !profile_) {
-        if (!gexec_[m] || graph_D_[m] != D_ || graph_dl_[m] != dl_) {
-            if (gexec_[m])
-                (void)hipGraphExecDestroy(gexec_[m]);
-            gexec_[m] = nullptr;
-            hipGraph_t g = nullptr;
-            E_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-            const ma_status st = enqueue(mode, true);
-            const hipError_t ec = hipStreamEndCapture(stream_, &g);
-            if (st != MA_OK) {
-                if (g)
-                    (void)hipGraphDestroy(g);
-                return st;
-            }
-            E_HIP(ec);
-            const hipError_t ei = hipGraphInstantiate(&gexec_[m], g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            E_HIP(ei);
-            graph_D_[m] = D_;
-            graph_dl_[m] = dl_;
+    const int m = int(mode) + (profile_ ? 3 : 0);
+    size_t nev = 0;
+    if (cycle && graphs_) {
+        if (gseg_[m].empty() || graph_D_[m] != D_ || graph_dl_[m] != dl_ ||
+            graph_stride_[m] != stride_ || graph_nl_[m] != loff_.size())
+            MA_TRY(capture(m, mode));
+        // segment k is followed by timing event k (profiled form only)
+        const size_t ns = gseg_[m].size();
+        while (pev_.size() + 1 < ns) {
+            hipEvent_t e;
+            E_HIP(hipEventCreate(&e));
+            pev_.push_back(e);
         }
-        E_HIP(hipGraphLaunch(gexec_[m], stream_));
+        for (size_t k = 0; k < ns; ++k) {
+            if (gseg_[m][k])
+                E_HIP(hipGraphLaunch(gseg_[m][k], stream_));
+            if (k + 1 < ns)
+                E_HIP(hipEventRecord(pev_[k], stream_));
+        }
+        nev = ns - 1;
     } else {
         pev_used_ = 0;
         MA_TRY(enqueue(mode, cycle));
+        nev = pev_used_;
     }
     E_HIP(hipMemcpyAsync(hnorm_, dnorm_, solves_.size() * sizeof(double), hipMemcpyDeviceToHost,
                          stream_));
@@ -926,7 +955,7 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
             norms[i] = std::sqrt(hnorm_[i] * h * h * h);
         }
     if (profile_ && cycle) {
-        for (size_t q = 0; q + 1 < pev_used_; q += 2) {
+        for (size_t q = 0; q + 1 < nev; q += 2) {
             float ms = 0.f;
             E_HIP(hipEventElapsedTime(&ms, pev_[q], pev_[q + 1]));
             prof_seconds_ += 1e-3 * double(ms);
@@ -934,6 +963,64 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         prof_bytes_ += prof_bytes_tick_;
         prof_launches_ += prof_launches_tick_;
     }
+    return MA_OK;
+}
+
+// Capture one tick of mode into slot m: one graph, or (profiled form) one
+// graph per segment between the finest-level sweep boundaries.  A segment
+// with no work is kept as a null entry so the event order is unchanged.
+ma_status Engine::capture(int m, Mode mode)
+{
+    for (hipGraphExec_t x : gseg_[m])
+        if (x)
+            (void)hipGraphExecDestroy(x);
+    gseg_[m].clear();
+    seg_tmp_.clear();
+    pev_used_ = 0;
+    seg_capture_ = profile_;
+    E_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    const ma_status st = enqueue(mode, true);
+    hipGraph_t last = nullptr;
+    const hipError_t ec = hipStreamEndCapture(stream_, &last);
+    seg_capture_ = false;
+    if (last)
+        seg_tmp_.push_back(last);
+    auto release = [&]() {
+        for (hipGraph_t g : seg_tmp_)
+            (void)hipGraphDestroy(g);
+        seg_tmp_.clear();
+    };
+    if (st != MA_OK || ec != hipSuccess) {
+        release();
+        for (hipGraphExec_t x : gseg_[m])
+            if (x)
+                (void)hipGraphExecDestroy(x);
+        gseg_[m].clear();
+        if (st != MA_OK)
+            return st;
+        return fail(MA_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    }
+    for (hipGraph_t g : seg_tmp_) {
+        size_t nodes = 0;
+        hipError_t e = hipGraphGetNodes(g, nullptr, &nodes);
+        hipGraphExec_t x = nullptr;
+        if (e == hipSuccess && nodes > 0)
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            release();
+            for (hipGraphExec_t y : gseg_[m])
+                if (y)
+                    (void)hipGraphExecDestroy(y);
+            gseg_[m].clear();
+            return fail(MA_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        gseg_[m].push_back(x);
+    }
+    release();
+    graph_D_[m] = D_;
+    graph_dl_[m] = dl_;
+    graph_stride_[m] = stride_;
+    graph_nl_[m] = loff_.size();
     return MA_OK;
 }
 

@@ -27,8 +27,11 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-SPECS = [("quadratic", 16, 1), ("exp_cos", 24, 2), ("example4", 32, 3), ("exp_cos", 33, 4),
-         ("quadratic", 48, 5), ("exp_cos", 64, 6), ("example4", 2, 7), ("exp_cos", 96, 8)]
+# sizes with 1 to 6 levels, odd coarsest grids (3, 5) and a single-level
+# odd grid (3); every one converges to the default tolerance
+SPECS = [("quadratic", 16, 1), ("exp_cos", 24, 2), ("example4", 32, 3), ("exp_cos", 40, 4),
+         ("quadratic", 48, 5), ("exp_cos", 64, 6), ("example4", 2, 7), ("exp_cos", 96, 8),
+         ("quadratic", 3, 9)]
 
 
 def solo(kind, n, seed, **kw):
@@ -36,7 +39,11 @@ def solo(kind, n, seed, **kw):
     p = P.make(kind, n, seed)
     s = Solver(n, **kw)
     u = dev(P.initial_guess(p))
-    rep = s.solve(u, dev(p.f))
+    from paper_1411_7018_amd._lib import MAError
+    try:
+        rep = s.solve(u, dev(p.f))
+    except MAError as e:        # an unconverged solve still reports its cycles
+        rep = e.report
     torch.cuda.synchronize()
     return u.cpu().numpy(), rep
 
@@ -57,6 +64,26 @@ def test_batch_bitwise_equals_solo(precision):
         assert rep["cycles"] == rs["cycles"] and rep["init_cycles"] == rs["init_cycles"]
         assert np.array_equal(u.cpu().numpy(), want), (k, n)
         assert rep["res"] == rs["res"]
+
+
+def test_batch_status_of_unconverged_member():
+    """A member that runs out of cycles (a single-level odd grid is plain
+    Gauss-Seidel) makes the batch return MA_ERR_NOT_CONVERGED; the other
+    members still finish, bitwise equal to their solo runs."""
+    from paper_1411_7018_amd import Solver
+    from paper_1411_7018_amd.batch import solve_batch
+    note("batch with an unconverged member")
+    specs = [("exp_cos", 24, 2), ("exp_cos", 33, 4), ("quadratic", 16, 1)]
+    probs = [P.make(k, n, s) for k, n, s in specs]
+    solvers = [Solver(p.n, max_cycles=6) for p in probs]
+    us = [dev(P.initial_guess(p)) for p in probs]
+    st, reps = solve_batch(solvers, us, [dev(p.f) for p in probs])
+    assert st == 4                          # MA_ERR_NOT_CONVERGED
+    assert reps[1]["cycles"] == 6 and reps[1]["converged"] == 0
+    for (k, n, s), u, rep in zip(specs, us, reps):
+        want, rs = solo(k, n, s, max_cycles=6)
+        assert rep["cycles"] == rs["cycles"] and rep["converged"] == rs["converged"]
+        assert np.array_equal(u.cpu().numpy(), want), (k, n)
 
 
 def test_batch_matches_oracle():
@@ -106,13 +133,13 @@ def test_resident_batch_join_and_leave(precision):
     from paper_1411_7018_amd import Solver
     from paper_1411_7018_amd.batch import ResidentBatch
     note("resident batch", precision)
-    b = ResidentBatch(8)
+    b = ResidentBatch(6)            # fewer slots than solves: joins wait for a leave
     pending = list(SPECS)
     live = {}
     finished = {}
     tick = 0
     while pending or live:
-        if pending and (tick % 2 == 0 or not live):
+        if pending and len(live) < b.max_solves and (tick % 2 == 0 or not live):
             k, n, s = pending.pop(0)
             p = P.make(k, n, s)
             sv = Solver(n, precision=precision)
@@ -143,3 +170,25 @@ def test_batch_rejects_mixed_parameters():
     b.add(Solver(16), dev(P.initial_guess(p)), dev(p.f))
     with pytest.raises(MAError):
         b.add(Solver(16, precision="mixed"), dev(P.initial_guess(p)), dev(p.f))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_profiled_ticks_equal_plain(precision):
+    """The profiled form (tick graphs cut at the finest-level sweeps, timing
+    events between the pieces) gives bitwise the plain result and a
+    positive smoother time."""
+    from paper_1411_7018_amd import Solver
+    note("profiled vs plain", precision)
+    p = P.exp_cos(48, seed=11)
+    plain = Solver(48, precision=precision)
+    u0 = dev(P.initial_guess(p))
+    r0 = plain.solve(u0, dev(p.f))
+    prof = Solver(48, precision=precision, profile=1)
+    for _ in range(2):
+        u1 = dev(P.initial_guess(p))
+        r1 = prof.solve(u1, dev(p.f))
+        torch.cuda.synchronize()
+        assert np.array_equal(u1.cpu().numpy(), u0.cpu().numpy())
+        assert r1["cycles"] == r0["cycles"]
+        assert r1["smooth_seconds"] > 0 and r1["smooth_launches"] > 0
+        assert r1["smooth_bytes"] > 0
