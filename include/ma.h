@@ -84,6 +84,10 @@ typedef struct {
     int tile_config;       /* fused sweep tile shape: 0 automatic, 1..6 fixed    */
     int zchunk;            /* fused sweep planes per z-chunk: 0 automatic        */
     int graphs;            /* 1: replay each cycle from a captured hipGraph      */
+    int coarse_n;          /* levels with n <= coarse_n (0..32) run inside one
+                              single-workgroup kernel per solve; 0: off         */
+    int max_blocks;        /* cap on the blocks of one batched launch (multiple
+                              of 8, 0 automatic = 16384)                         */
 } ma_params;
 
 typedef struct {

@@ -33,7 +33,8 @@ class ma_params(ctypes.Structure):
                 ("init_tol", ctypes.c_double), ("init_max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("profile", ctypes.c_int),
                 ("tile_config", ctypes.c_int), ("zchunk", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("coarse_n", ctypes.c_int),
+                ("max_blocks", ctypes.c_int)]
 
 
 class ma_report(ctypes.Structure):

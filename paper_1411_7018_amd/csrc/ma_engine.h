@@ -1,11 +1,13 @@
 // Batched execution engine.  Every level phase of the FAS V-cycle
 // (Algorithm 1) -- a colour phase of a sweep, the residual, the FAS
 // restriction, the prolongation, the norm -- runs for ALL solves of a batch
-// as ONE launch over a device-resident table of grids.  The launches use a
-// fixed number of persistent blocks, so one V-cycle (a "tick") has a static
-// shape that is captured once into a hipGraph and replayed; a change of the
-// batch composition only rewrites the device tables.  A single solve is a
-// batch of one.
+// as ONE launch over a device-resident table of grids.  The levels of every
+// solve whose size is at most coarse_n (the coarse end of each V-cycle) run
+// instead inside ONE kernel with one workgroup per solve, the phases
+// separated by workgroup barriers.  One V-cycle (a "tick") therefore has a
+// static shape that is captured once into a hipGraph and replayed; a change
+// of the batch composition only rewrites the device tables.  A single solve
+// is a batch of one.
 #pragma once
 
 #include "ma_runtime.h"
@@ -14,8 +16,10 @@
 
 namespace mafas {
 
-constexpr int kMaxGrids = 64;         // grids (solve, level) per batched launch
-constexpr int kPersistBlocks = 4096;  // blocks of 64 threads in every batched launch
+constexpr int kMaxGrids = 64;          // grids (solve, level) per batched launch
+constexpr int kDefaultMaxBlocks = 16384;
+constexpr int kTailThreads = 512;      // threads of the coarse-level kernel
+constexpr int kMaxTail = 6;            // levels per solve inside that kernel
 
 // One grid of one solve inside a batched launch.  The grid's work items are
 // [start, start + gx*gy*gz), item = bx + gx*(by + gy*bz); every item is one
@@ -41,6 +45,23 @@ struct BatchList {
 };
 constexpr size_t list_bytes(int ngrids) { return 16 + sizeof(GridItem) * size_t(ngrids); }
 
+// The coarse levels of one solve: per level the descriptors of its sweep,
+// residual, restriction (to the next level) and prolongation (from it).
+struct TailLevel {
+    GridItem sw, res, rst, pro;
+};
+struct TailEntry {
+    int nlev;
+    int pad[3];
+    TailLevel lv[kMaxTail];
+};
+struct TailList {
+    int nsolves;
+    int pad[3];
+    TailEntry e[kMaxGrids];
+};
+constexpr size_t tail_bytes(int nsolves) { return 16 + sizeof(TailEntry) * size_t(nsolves); }
+
 enum ListKind {
     LK_SWEEP,      // p: u, F                        items: rows of one colour
     LK_RESIDUAL,   // p: u, F, r                     items: interior rows
@@ -59,11 +80,16 @@ enum ListKind {
 
 void item_dims(int kind, int order, int n, int *gx, int *gy, int *gz);
 
+// blocks: grid size (a multiple of 8; blocks are split evenly over the XCDs)
 hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color, int rmode,
-                          const BatchList *dlist, unsigned long long *ncount,
+                          const BatchList *dlist, int blocks, unsigned long long *ncount,
                           unsigned long long *nfall);
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, const double *partials,
                                  double *out);
+// one workgroup per TailList entry (blocks >= entries); mode: Engine::Mode
+hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const TailList *T,
+                       int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount,
+                       unsigned long long *nfall);
 
 struct SolveRef {
     ma_solver *s = nullptr;
@@ -81,8 +107,9 @@ class Engine {
     Engine &operator=(const Engine &) = delete;
 
     // Define the solves (at most kMaxGrids) and the stream the caller orders
-    // its work on.  All solvers must share nu1, nu2, nu0, order, restriction
-    // and precision.  graphs: replay ticks from captured hipGraphs.
+    // its work on.  All solvers must share nu1, nu2, nu0, order, restriction,
+    // precision, inner_cycles, coarse_n and max_blocks.  graphs: replay
+    // ticks from captured hipGraphs.
     ma_status set(const std::vector<SolveRef> &solves, hipStream_t user, bool graphs,
                   bool profile);
     // One V-cycle (MA, LAP) or one outer correction (MIXED) of every active
@@ -119,19 +146,29 @@ class Engine {
     const double *level_u(int i, int l, Mode mode) const;
     const double *level_F(int i, int l, Mode mode) const;
     GridItem grid(int kind, int i, int l, Mode mode) const;
+    int levels(int i) const;
+    int multiblock_levels(int i) const;  // leading levels with n > coarse_n
+    ma_status capture(int slot, Mode mode);
+    std::vector<int> shape() const;
+    ma_status prof_mark();
 
     std::vector<SolveRef> solves_;
     hipStream_t user_ = nullptr, stream_ = nullptr;
     hipEvent_t ev_in_ = nullptr;
     bool graphs_ = true, profile_ = false, fused_ = false;
     std::string err_;
-    int D_ = 0;
+    int D_ = 0;      // multi-block depth of the active solves
+    int Dall_ = 0;   // full depth of the active solves
     int nu1_ = 2, nu2_ = 2, nu0_ = 1, order_ = 0, rmode_ = 0, inner_ = 2;
+    int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks;
 
-    std::vector<char> hbuf_;               // packed host copy of the lists
+    std::vector<char> hbuf_;               // host copy of the lists and the tail table
     std::vector<size_t> loff_;             // byte offset of each list
     std::vector<int> lng_;                 // grids per list
-    char *dl_ = nullptr;                   // packed device lists
+    std::vector<int> lgrid_;               // blocks per list launch (0: never any grid)
+    size_t toff_ = 0;                      // byte offset of the tail table
+    int tail_blocks_ = 0;                  // blocks of the tail launch (0: no tail)
+    char *dl_ = nullptr;                   // device lists
     size_t dl_cap_ = 0;
     char *hstage_ = nullptr;               // pinned staging for uploads
     size_t hstage_cap_ = 0;
@@ -152,16 +189,15 @@ class Engine {
     // Captured ticks, one slot per mode; slot mode + 3 is the profiled form:
     // the tick split into segments at the finest-level sweep boundaries, so
     // the timing events are recorded on the stream between segment launches.
+    // A graph is replayed only while the launch shapes it was captured with
+    // (depths, list table address and stride, blocks per launch) still hold.
     static constexpr int kSlots = 6;
     std::vector<hipGraphExec_t> gseg_[kSlots];
-    int graph_D_[kSlots] = {-1, -1, -1, -1, -1, -1};
+    std::vector<int> graph_shape_[kSlots];
     const char *graph_dl_[kSlots] = {};
-    size_t graph_stride_[kSlots] = {};   // list stride a graph was captured with
-    size_t graph_nl_[kSlots] = {};       // list count a graph was captured with
     size_t stride_ = 0;                  // bytes per list: list_bytes(slots)
     bool seg_capture_ = false;           // prof_mark() cuts the capture
     std::vector<hipGraph_t> seg_tmp_;
-    ma_status capture(int slot, Mode mode);
 
     std::vector<hipEvent_t> pev_;          // profile event pairs (finest sweeps)
     size_t pev_used_ = 0;
@@ -169,7 +205,6 @@ class Engine {
     int prof_launches_ = 0;
     double prof_bytes_tick_ = 0.0;
     int prof_launches_tick_ = 0;
-    ma_status prof_mark();
 };
 
 } // namespace mafas

@@ -1,10 +1,20 @@
-// Batched execution engine (see ma_engine.h).  The device side is one kernel
-// template: a fixed grid of kPersistBlocks single-wave blocks walks the work
-// items of a BatchList; each item is one x-row of 64 nodes of one grid.  The
-// items are split into 8 contiguous chunks, one per XCD (blocks are
-// dispatched round-robin over XCDs), so the rows a stencil reads as halos
-// are processed on the same XCD at about the same time and share its L2.
-// The point arithmetic is the same device code as the single-grid kernels.
+// Batched execution engine (see ma_engine.h).
+//
+// Device side.  The per-node arithmetic of every phase (sweep update,
+// residual, FAS restriction with the tau-corrected coarse right-hand side,
+// prolongation, and their FP32 mixed-precision counterparts) is written once
+// below as pt_* functions.  Two kernels drive them:
+//   k_batched  single-wave blocks walk the work items of a BatchList, one
+//              x-row segment of 64 nodes per item.  The items are split into
+//              8 contiguous chunks, one per XCD (blocks are dispatched
+//              round-robin over XCDs), so rows that read each other as
+//              stencil halos are processed on one XCD and share its L2.
+//   k_tail     one workgroup per solve runs all of that solve's coarse
+//              levels (down, coarsest sweeps, up) with workgroup barriers
+//              between phases, replacing dozens of tiny launches.
+// Both call the same pt_* code, so a node's update is bitwise the same
+// whichever kernel runs it; inside one colour phase the nodes are
+// independent, so the order in which they are visited does not matter.
 #include "ma_engine.h"
 #include "ma_mixed_device.h"
 
@@ -23,10 +33,176 @@ __device__ __forceinline__ double wave_sum64(double v)
     return v;
 }
 
-// Colour rows: (bx, by, bz) -> first node (i, j, k) of the row segment.
+// ---------------------------------------------------------------------------
+// Per-node phases.  p is the node's linear index, (sy, sz) the strides of
+// G's grid.
+// ---------------------------------------------------------------------------
+template <int OP>
+__device__ __forceinline__ void pt_sweep(const GridItem &G, long p, long sy, long sz,
+                                         unsigned long long *__restrict__ ncount)
+{
+    double *u = static_cast<double *>(G.p[0]);
+    const double *F = static_cast<const double *>(G.p[1]);
+    if (OP == OP_MA) {
+        const Hess g = hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s);
+        bool nc = false;
+        u[p] = ma_point_update(g, u[p], F[p], G.hk, nc);
+        if (nc)
+            atomicAdd(ncount + G.slot, 1ull);
+    } else {
+        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, G.s), u[p], F[p], G.hk);
+    }
+}
+
+template <int OP>
+__device__ __forceinline__ double pt_resid(const GridItem &G, long p, long sy, long sz)
+{
+    const double *u = static_cast<const double *>(G.p[0]);
+    const double *F = static_cast<const double *>(G.p[1]);
+    if (OP == OP_MA)
+        return F[p] - det3(hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s));
+    return F[p] - laplacian_at(u, p, 1, sy, sz, G.s);
+}
+
+// FAS restriction at coarse node (I, J, K) of the fine grid G.n: injection
+// of u into w_H and u_H, and b_H = S_H(w_H) + I_h^H r at coarse interior
+// nodes (Algorithm 1, step 3).
+template <int OP, int RMODE>
+__device__ __forceinline__ void pt_restrict(const GridItem &G, int I, int J, int K)
+{
+    const int nf = G.n, nc = nf / 2;
+    const double *uf = static_cast<const double *>(G.p[0]);
+    const double *rf = static_cast<const double *>(G.p[1]);
+    const long fy = nf + 1, fz = fy * fy, cy = nc + 1, cz = cy * cy;
+    const long f = 2 * I + fy * (2 * J) + fz * (2 * K);
+    const long c = I + cy * J + cz * K;
+    const double v = uf[f];
+    static_cast<double *>(G.p[2])[c] = v;
+    static_cast<double *>(G.p[3])[c] = v;
+    double b = 0.0;
+    if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
+        double rh;
+        if (RMODE == 0) {
+            const double w[3] = {0.25, 0.5, 0.25};
+            rh = 0.0;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        rh += (w[dz + 1] * w[dy + 1] * w[dx + 1]) * rf[f + dx + fy * dy + fz * dz];
+        } else {
+            rh = (6.0 * rf[f] + (rf[f - 1] + rf[f + 1]) + (rf[f - fy] + rf[f + fy])
+                  + (rf[f - fz] + rf[f + fz])) / 12.0;
+        }
+        const double sc = double(nc) * double(nc);
+        double sh;
+        if (OP == OP_MA)
+            sh = det3(hessian_at(uf, f, 2, 2 * fy, 2 * fz, sc, 0.25 * sc));
+        else
+            sh = laplacian_at(uf, f, 2, 2 * fy, 2 * fz, sc);
+        b = sh + rh;
+    }
+    static_cast<double *>(G.p[4])[c] = b;
+}
+
+// Trilinear prolongation of the coarse correction (u_H - w_H) added at
+// fine interior node (i, j, k) (Algorithm 1, step 5).  T: double or float.
+template <typename T>
+__device__ __forceinline__ void pt_prolong(const GridItem &G, int i, int j, int k)
+{
+    const int nf = G.n, nc = nf / 2;
+    const long sy = nf + 1, sz = sy * sy, cy = nc + 1, cz = cy * cy;
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+    const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
+    const long p = i + sy * j + sz * k;
+    const T *uc = static_cast<const T *>(G.p[1]);
+    const T *wc = static_cast<const T *>(G.p[2]);
+    const T one = T(1), half = T(0.5);
+    const T wi = (i & 1) ? half : one, wj = (j & 1) ? half : one, wk = (k & 1) ? half : one;
+    T d = T(0);
+    for (int c = 0; c < nk; ++c)
+        for (int b = 0; b < nj; ++b)
+            for (int a = 0; a < ni; ++a) {
+                const long q = (I0 + a) + cy * (J0 + b) + cz * (K0 + c);
+                d += (wk * wj * wi) * (uc[q] - wc[q]);
+            }
+    static_cast<T *>(G.p[0])[p] += d;
+}
+
+__device__ __forceinline__ void pt_msweep(const GridItem &G, long p, long sy, long sz,
+                                          unsigned long long *__restrict__ ncount,
+                                          unsigned long long *__restrict__ nfall)
+{
+    float *d = static_cast<float *>(G.p[0]);
+    const float *b = static_cast<const float *>(G.p[1]);
+    const double *U = static_cast<const double *>(G.p[2]);
+    const LevelConst lc = level_const(G.n);
+    bool fb = false, nc = false;
+    d[p] = mixed_point(d, U, b[p], p, sy, sz, lc.s, lc.s4, lc.sf, lc.s4f, lc.hkf, fb, nc);
+    if (fb)
+        atomicAdd(nfall + G.slot, 1ull);
+    if (nc)
+        atomicAdd(ncount + G.slot, 1ull);
+}
+
+__device__ __forceinline__ void pt_mresid(const GridItem &G, long p, long sy, long sz)
+{
+    const float *d = static_cast<const float *>(G.p[0]);
+    const float *b = static_cast<const float *>(G.p[1]);
+    const double *U = static_cast<const double *>(G.p[2]);
+    const LevelConst lc = level_const(G.n);
+    const Sym32 H = to32(hessian_at(U, p, 1, sy, sz, lc.s, lc.s4));
+    const Sym32 E = hess32(d, p, 1, sy, sz, lc.sf, lc.s4f);
+    static_cast<float *>(G.p[3])[p] = b[p] - t_of(H, adj32(H), E);
+}
+
+template <int RMODE>
+__device__ __forceinline__ void pt_mrestrict(const GridItem &G, int I, int J, int K)
+{
+    const int nf = G.n, nc = nf / 2;
+    const float *df = static_cast<const float *>(G.p[0]);
+    const float *rf = static_cast<const float *>(G.p[1]);
+    const double *Uc = static_cast<const double *>(G.p[2]);
+    const long fy = nf + 1, fz = fy * fy, cy = nc + 1, cz = cy * cy;
+    const long f = 2 * I + fy * (2 * J) + fz * (2 * K);
+    const long c = I + cy * J + cz * K;
+    const float v = df[f];
+    static_cast<float *>(G.p[3])[c] = v;
+    static_cast<float *>(G.p[4])[c] = v;
+    float bv = 0.0f;
+    if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
+        float rh;
+        if (RMODE == 0) {
+            const float w[3] = {0.25f, 0.5f, 0.25f};
+            rh = 0.0f;
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        rh += (w[dz + 1] * w[dy + 1] * w[dx + 1]) * rf[f + dx + fy * dy + fz * dz];
+        } else {
+            rh = (6.0f * rf[f] + (rf[f - 1] + rf[f + 1]) + (rf[f - fy] + rf[f + fy])
+                  + (rf[f - fz] + rf[f + fz])) * (1.0f / 12.0f);
+        }
+        const LevelConst lcc = level_const(nc);
+        const Sym32 H = to32(hessian_at(Uc, c, 1, cy, cz, lcc.s, lcc.s4));
+        const Sym32 E = hess32(df, f, 2, 2 * fy, 2 * fz, lcc.sf, lcc.s4f);
+        bv = t_of(H, adj32(H), E) + rh;
+    }
+    static_cast<float *>(G.p[5])[c] = bv;
+}
+
+// ---------------------------------------------------------------------------
+// Row kernel: work item (bx, by, bz) of grid G, lane t.
+// ---------------------------------------------------------------------------
+// Colour rows: (bx, by, bz) -> node (i, j, k) of lane t.
 template <int ORDER>
-__device__ __forceinline__ void colour_row(int color, int bx, int by, int bz, int &i, int &j,
-                                           int &k)
+__device__ __forceinline__ void colour_row(int color, int bx, int by, int bz, int t, int &i,
+                                           int &j, int &k)
 {
     int i0;
     if (ORDER == 0) {
@@ -39,45 +215,32 @@ __device__ __forceinline__ void colour_row(int color, int bx, int by, int bz, in
         k = ((color >> 2) & 1 ? 1 : 2) + 2 * bz;
         i0 = (color & 1) ? 1 : 2;
     }
-    i = i0 + 2 * (bx * 64 + int(threadIdx.x));
+    i = i0 + 2 * (bx * 64 + t);
 }
 
 template <int KIND, int OP, int ORDER, int RMODE>
 __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int bz, int color,
-                                         unsigned long long *__restrict__ ncount,
+                                         int t, unsigned long long *__restrict__ ncount,
                                          unsigned long long *__restrict__ nfall)
 {
     const int n = G.n;
     const long sy = n + 1, sz = sy * sy;
-    const int t = threadIdx.x;
-    if (KIND == LK_SWEEP) {
+    if (KIND == LK_SWEEP || KIND == LK_MSWEEP) {
         int i, j, k;
-        colour_row<ORDER>(color, bx, by, bz, i, j, k);
+        colour_row<ORDER>(color, bx, by, bz, t, i, j, k);
         if (i <= n - 1 && j <= n - 1 && k <= n - 1) {
-            double *u = static_cast<double *>(G.p[0]);
-            const double *F = static_cast<const double *>(G.p[1]);
             const long p = i + sy * j + sz * k;
-            if (OP == OP_MA) {
-                const Hess g = hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s);
-                bool nc = false;
-                u[p] = ma_point_update(g, u[p], F[p], G.hk, nc);
-                if (nc)
-                    atomicAdd(ncount + G.slot, 1ull);
-            } else {
-                u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, G.s), u[p], F[p], G.hk);
-            }
+            if (KIND == LK_SWEEP)
+                pt_sweep<OP>(G, p, sy, sz, ncount);
+            else
+                pt_msweep(G, p, sy, sz, ncount, nfall);
         }
     } else if (KIND == LK_RESIDUAL || KIND == LK_NORM || KIND == LK_RES32) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
         double rv = 0.0;
         if (i <= n - 1) {
-            const double *u = static_cast<const double *>(G.p[0]);
-            const double *F = static_cast<const double *>(G.p[1]);
             const long p = i + sy * j + sz * k;
-            if (OP == OP_MA)
-                rv = F[p] - det3(hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s));
-            else
-                rv = F[p] - laplacian_at(u, p, 1, sy, sz, G.s);
+            rv = pt_resid<OP>(G, p, sy, sz);
             if (KIND == LK_RESIDUAL)
                 static_cast<double *>(G.p[2])[p] = rv;
             if (KIND == LK_RES32)
@@ -91,156 +254,32 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
                 part[G.pbase + local] = sum;
             }
         }
-    } else if (KIND == LK_RESTRICT) {
-        const int nf = n, nc = nf / 2;
+    } else if (KIND == LK_RESTRICT || KIND == LK_MRESTRICT || KIND == LK_INJECT) {
+        const int nc = n / 2;
         const int I = bx * 64 + t, J = by, K = bz;
         if (I <= nc) {
-            const double *uf = static_cast<const double *>(G.p[0]);
-            const double *rf = static_cast<const double *>(G.p[1]);
-            const long fy = nf + 1, fz = fy * fy, cy = nc + 1, cz = cy * cy;
-            const long f = 2 * I + fy * (2 * J) + fz * (2 * K);
-            const long c = I + cy * J + cz * K;
-            const double v = uf[f];
-            static_cast<double *>(G.p[2])[c] = v;
-            static_cast<double *>(G.p[3])[c] = v;
-            double b = 0.0;
-            if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
-                double rh;
-                if (RMODE == 0) {
-                    const double w[3] = {0.25, 0.5, 0.25};
-                    rh = 0.0;
-#pragma unroll
-                    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                            for (int dx = -1; dx <= 1; ++dx)
-                                rh += (w[dz + 1] * w[dy + 1] * w[dx + 1])
-                                      * rf[f + dx + fy * dy + fz * dz];
-                } else {
-                    rh = (6.0 * rf[f] + (rf[f - 1] + rf[f + 1]) + (rf[f - fy] + rf[f + fy])
-                          + (rf[f - fz] + rf[f + fz])) / 12.0;
-                }
-                const double sc = double(nc) * double(nc);
-                double sh;
-                if (OP == OP_MA)
-                    sh = det3(hessian_at(uf, f, 2, 2 * fy, 2 * fz, sc, 0.25 * sc));
-                else
-                    sh = laplacian_at(uf, f, 2, 2 * fy, 2 * fz, sc);
-                b = sh + rh;
+            if (KIND == LK_RESTRICT)
+                pt_restrict<OP, RMODE>(G, I, J, K);
+            else if (KIND == LK_MRESTRICT)
+                pt_mrestrict<RMODE>(G, I, J, K);
+            else {
+                const long fy = n + 1, cy = nc + 1;
+                static_cast<double *>(G.p[1])[I + cy * J + cy * cy * K] =
+                    static_cast<const double *>(G.p[0])[2 * I + fy * (2 * J) + fy * fy * (2 * K)];
             }
-            static_cast<double *>(G.p[4])[c] = b;
         }
     } else if (KIND == LK_PROLONG || KIND == LK_MPROLONG) {
-        const int nf = n, nc = nf / 2;
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
-        if (i <= nf - 1) {
-            const long cy = nc + 1, cz = cy * cy;
-            const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
-            const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
-            const long p = i + sy * j + sz * k;
-            if (KIND == LK_PROLONG) {
-                const double *uc = static_cast<const double *>(G.p[1]);
-                const double *wc = static_cast<const double *>(G.p[2]);
-                const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0,
-                             wk = (k & 1) ? 0.5 : 1.0;
-                double d = 0.0;
-                for (int c = 0; c < nk; ++c)
-                    for (int b = 0; b < nj; ++b)
-                        for (int a = 0; a < ni; ++a) {
-                            const long q = (I0 + a) + cy * (J0 + b) + cz * (K0 + c);
-                            d += (wk * wj * wi) * (uc[q] - wc[q]);
-                        }
-                static_cast<double *>(G.p[0])[p] += d;
-            } else {
-                const float *dc = static_cast<const float *>(G.p[1]);
-                const float *wc = static_cast<const float *>(G.p[2]);
-                const float wi = (i & 1) ? 0.5f : 1.0f, wj = (j & 1) ? 0.5f : 1.0f,
-                            wk = (k & 1) ? 0.5f : 1.0f;
-                float d = 0.0f;
-                for (int c = 0; c < nk; ++c)
-                    for (int b = 0; b < nj; ++b)
-                        for (int a = 0; a < ni; ++a) {
-                            const long q = (I0 + a) + cy * (J0 + b) + cz * (K0 + c);
-                            d += (wk * wj * wi) * (dc[q] - wc[q]);
-                        }
-                static_cast<float *>(G.p[0])[p] += d;
-            }
-        }
-    } else if (KIND == LK_MSWEEP) {
-        int i, j, k;
-        colour_row<ORDER>(color, bx, by, bz, i, j, k);
-        if (i <= n - 1 && j <= n - 1 && k <= n - 1) {
-            float *d = static_cast<float *>(G.p[0]);
-            const float *b = static_cast<const float *>(G.p[1]);
-            const double *U = static_cast<const double *>(G.p[2]);
-            const long p = i + sy * j + sz * k;
-            const LevelConst lc = level_const(n);
-            bool fb = false, nc = false;
-            d[p] = mixed_point(d, U, b[p], p, sy, sz, lc.s, lc.s4, lc.sf, lc.s4f, lc.hkf, fb, nc);
-            if (fb)
-                atomicAdd(nfall + G.slot, 1ull);
-            if (nc)
-                atomicAdd(ncount + G.slot, 1ull);
+        if (i <= n - 1) {
+            if (KIND == LK_PROLONG)
+                pt_prolong<double>(G, i, j, k);
+            else
+                pt_prolong<float>(G, i, j, k);
         }
     } else if (KIND == LK_MRESIDUAL) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
-        if (i <= n - 1) {
-            const float *d = static_cast<const float *>(G.p[0]);
-            const float *b = static_cast<const float *>(G.p[1]);
-            const double *U = static_cast<const double *>(G.p[2]);
-            const long p = i + sy * j + sz * k;
-            const LevelConst lc = level_const(n);
-            const Sym32 H = to32(hessian_at(U, p, 1, sy, sz, lc.s, lc.s4));
-            const Sym32 E = hess32(d, p, 1, sy, sz, lc.sf, lc.s4f);
-            static_cast<float *>(G.p[3])[p] = b[p] - t_of(H, adj32(H), E);
-        }
-    } else if (KIND == LK_MRESTRICT) {
-        const int nf = n, nc = nf / 2;
-        const int I = bx * 64 + t, J = by, K = bz;
-        if (I <= nc) {
-            const float *df = static_cast<const float *>(G.p[0]);
-            const float *rf = static_cast<const float *>(G.p[1]);
-            const double *Uc = static_cast<const double *>(G.p[2]);
-            const long fy = nf + 1, fz = fy * fy, cy = nc + 1, cz = cy * cy;
-            const long f = 2 * I + fy * (2 * J) + fz * (2 * K);
-            const long c = I + cy * J + cz * K;
-            const float v = df[f];
-            static_cast<float *>(G.p[3])[c] = v;
-            static_cast<float *>(G.p[4])[c] = v;
-            float bv = 0.0f;
-            if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
-                float rh;
-                if (RMODE == 0) {
-                    const float w[3] = {0.25f, 0.5f, 0.25f};
-                    rh = 0.0f;
-#pragma unroll
-                    for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                        for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                            for (int dx = -1; dx <= 1; ++dx)
-                                rh += (w[dz + 1] * w[dy + 1] * w[dx + 1])
-                                      * rf[f + dx + fy * dy + fz * dz];
-                } else {
-                    rh = (6.0f * rf[f] + (rf[f - 1] + rf[f + 1]) + (rf[f - fy] + rf[f + fy])
-                          + (rf[f - fz] + rf[f + fz])) * (1.0f / 12.0f);
-                }
-                const LevelConst lcc = level_const(nc);
-                const Sym32 H = to32(hessian_at(Uc, c, 1, cy, cz, lcc.s, lcc.s4));
-                const Sym32 E = hess32(df, f, 2, 2 * fy, 2 * fz, lcc.sf, lcc.s4f);
-                bv = t_of(H, adj32(H), E) + rh;
-            }
-            static_cast<float *>(G.p[5])[c] = bv;
-        }
-    } else if (KIND == LK_INJECT) {
-        const int nf = n, nc = nf / 2;
-        const int I = bx * 64 + t, J = by, K = bz;
-        if (I <= nc) {
-            const long fy = nf + 1, cy = nc + 1;
-            static_cast<double *>(G.p[1])[I + cy * J + cy * cy * K] =
-                static_cast<const double *>(G.p[0])[2 * I + fy * (2 * J) + fy * fy * (2 * K)];
-        }
+        if (i <= n - 1)
+            pt_mresid(G, i + sy * j + sz * k, sy, sz);
     } else if (KIND == LK_ACCUM) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
         if (i <= n - 1) {
@@ -254,12 +293,13 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
     }
 }
 
+// gridDim.x is a multiple of 8: gridDim.x / 8 blocks per XCD chunk.
 template <int KIND, int OP, int ORDER, int RMODE>
 __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L, int color,
                                                 unsigned long long *__restrict__ ncount,
                                                 unsigned long long *__restrict__ nfall)
 {
-    constexpr int kBlocksPerXcd = kPersistBlocks / 8;
+    const int bpx = int(gridDim.x >> 3);
     const int total = L->total;
     const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
     const int per = (total + 7) >> 3;
@@ -278,7 +318,7 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
             g1 = mid - 1;
     }
     int g = g0;
-    for (; it < hi; it += kBlocksPerXcd) {
+    for (; it < hi; it += bpx) {
         while (g + 1 < ng && L->g[g + 1].start <= it)
             ++g;
         const GridItem &G = L->g[g];
@@ -287,16 +327,18 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
         const int rest = local / G.gx;
         const int by = rest % G.gy;
         const int bz = rest / G.gy;
-        run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, ncount, nfall);
+        run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, int(threadIdx.x), ncount, nfall);
     }
 }
 
-// Fixed-order per-grid sum of the partials of a norm list.
-__global__ __launch_bounds__(256) void k_batched_reduce(const BatchList *__restrict__ L,
-                                                        const double *__restrict__ partials,
-                                                        double *__restrict__ out)
+// Fixed-order per-grid sum of the partials of a norm list: thread t adds
+// partials t, t + 1024, ... in order, then a fixed shuffle tree per wave and
+// the 16 wave sums in order.
+__global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__restrict__ L,
+                                                         const double *__restrict__ partials,
+                                                         double *__restrict__ out)
 {
-    __shared__ double part[4];
+    __shared__ double part[16];
     const int g = blockIdx.x;
     if (g >= L->ngrids)
         return;
@@ -304,21 +346,148 @@ __global__ __launch_bounds__(256) void k_batched_reduce(const BatchList *__restr
     const int end = (g + 1 < L->ngrids) ? L->g[g + 1].start : L->total;
     const int cnt = end - G.start;
     double v = 0.0;
-    for (int q = threadIdx.x; q < cnt; q += 256)
+    for (int q = threadIdx.x; q < cnt; q += 1024)
         v += partials[G.pbase + q];
     v = wave_sum64(v);
     if ((threadIdx.x & 63) == 0)
         part[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0)
-        out[G.slot] = ((part[0] + part[1]) + part[2]) + part[3];
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < 16; ++w)
+            s += part[w];
+        out[G.slot] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-level kernel: one workgroup runs the coarse end of one solve's
+// V-cycle.  Nodes are enumerated densely per phase (a colour class has at
+// most (n/2)^2 (n-1) or (n/2)^3 candidates), since the rows of a coarse
+// grid are far shorter than a wavefront.
+// ---------------------------------------------------------------------------
+template <int OP, bool MIXED, int ORDER>
+__device__ __forceinline__ void tail_sweep(const GridItem &G, int color,
+                                           unsigned long long *__restrict__ ncount,
+                                           unsigned long long *__restrict__ nfall)
+{
+    const int n = G.n, hn = n / 2;
+    const long sy = n + 1, sz = sy * sy;
+    const int cnt = ORDER == 0 ? hn * hn * (n - 1) : hn * hn * hn;
+    for (int q = threadIdx.x; q < cnt; q += kTailThreads) {
+        const int ii = q % hn, r = q / hn;
+        const int jj = r % hn, kk = r / hn;
+        int i, j, k;
+        if (ORDER == 0) {
+            const int c0 = color & 1, c1 = color >> 1;
+            k = 1 + kk;
+            j = (((c0 + c1 + k) & 1) ? 1 : 2) + 2 * jj;
+            i = (((c0 + j) & 1) ? 1 : 2) + 2 * ii;
+        } else {
+            i = ((color & 1) ? 1 : 2) + 2 * ii;
+            j = (((color >> 1) & 1) ? 1 : 2) + 2 * jj;
+            k = (((color >> 2) & 1) ? 1 : 2) + 2 * kk;
+        }
+        if (i <= n - 1 && j <= n - 1 && k <= n - 1) {
+            const long p = i + sy * j + sz * k;
+            if (MIXED)
+                pt_msweep(G, p, sy, sz, ncount, nfall);
+            else
+                pt_sweep<OP>(G, p, sy, sz, ncount);
+        }
+    }
+}
+
+template <int OP, bool MIXED>
+__device__ __forceinline__ void tail_residual(const GridItem &G)
+{
+    const int n = G.n, m = n - 1;
+    const long sy = n + 1, sz = sy * sy;
+    const int cnt = m * m * m;
+    for (int q = threadIdx.x; q < cnt; q += kTailThreads) {
+        const int i = 1 + q % m, r = q / m;
+        const int j = 1 + r % m, k = 1 + r / m;
+        const long p = i + sy * j + sz * k;
+        if (MIXED)
+            pt_mresid(G, p, sy, sz);
+        else
+            static_cast<double *>(G.p[2])[p] = pt_resid<OP>(G, p, sy, sz);
+    }
+}
+
+template <int OP, bool MIXED, int RMODE>
+__device__ __forceinline__ void tail_restrict(const GridItem &G)
+{
+    const int m = G.n / 2 + 1;
+    const int cnt = m * m * m;
+    for (int q = threadIdx.x; q < cnt; q += kTailThreads) {
+        const int I = q % m, r = q / m;
+        const int J = r % m, K = r / m;
+        if (MIXED)
+            pt_mrestrict<RMODE>(G, I, J, K);
+        else
+            pt_restrict<OP, RMODE>(G, I, J, K);
+    }
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void tail_prolong(const GridItem &G)
+{
+    const int m = G.n - 1;
+    const int cnt = m * m * m;
+    for (int q = threadIdx.x; q < cnt; q += kTailThreads) {
+        const int i = 1 + q % m, r = q / m;
+        const int j = 1 + r % m, k = 1 + r / m;
+        if (MIXED)
+            pt_prolong<float>(G, i, j, k);
+        else
+            pt_prolong<double>(G, i, j, k);
+    }
+}
+
+// Every thread of the block reaches every barrier below: all loop bounds
+// depend only on the block's table entry and the sweep counts.
+template <int OP, bool MIXED, int ORDER, int RMODE>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailList *__restrict__ T, int nu1,
+                                                       int nu2, int nu0,
+                                                       unsigned long long *__restrict__ ncount,
+                                                       unsigned long long *__restrict__ nfall)
+{
+    if (int(blockIdx.x) >= T->nsolves)
+        return;
+    const TailEntry &E = T->e[blockIdx.x];
+    const int L = E.nlev;
+    constexpr int colours = ORDER == 0 ? 4 : 8;
+    for (int l = 0; l < L; ++l) {
+        const int cnt = l < L - 1 ? nu1 : nu0;
+        for (int s = 0; s < cnt; ++s)
+            for (int c = 0; c < colours; ++c) {
+                tail_sweep<OP, MIXED, ORDER>(E.lv[l].sw, c, ncount, nfall);
+                __syncthreads();
+            }
+        if (l < L - 1) {
+            tail_residual<OP, MIXED>(E.lv[l].res);
+            __syncthreads();
+            tail_restrict<OP, MIXED, RMODE>(E.lv[l].rst);
+            __syncthreads();
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        tail_prolong<MIXED>(E.lv[l].pro);
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s)
+            for (int c = 0; c < colours; ++c) {
+                tail_sweep<OP, MIXED, ORDER>(E.lv[l].sw, c, ncount, nfall);
+                __syncthreads();
+            }
+    }
 }
 
 template <int KIND, int OP>
 hipError_t launch_k(hipStream_t st, int order, int color, int rmode, const BatchList *L,
-                    unsigned long long *nc, unsigned long long *nf)
+                    int blocks, unsigned long long *nc, unsigned long long *nf)
 {
-    const dim3 grid(kPersistBlocks), block(64);
+    const dim3 grid(blocks), block(64);
     if (order == 0) {
         if (rmode == 0)
             hipLaunchKernelGGL((k_batched<KIND, OP, 0, 0>), grid, block, 0, st, L, color, nc, nf);
@@ -335,11 +504,34 @@ hipError_t launch_k(hipStream_t st, int order, int color, int rmode, const Batch
 
 template <int KIND>
 hipError_t launch_kind(hipStream_t st, int op, int order, int color, int rmode, const BatchList *L,
-                       unsigned long long *nc, unsigned long long *nf)
+                       int blocks, unsigned long long *nc, unsigned long long *nf)
 {
     if (op == OP_MA)
-        return launch_k<KIND, OP_MA>(st, order, color, rmode, L, nc, nf);
-    return launch_k<KIND, OP_LAP>(st, order, color, rmode, L, nc, nf);
+        return launch_k<KIND, OP_MA>(st, order, color, rmode, L, blocks, nc, nf);
+    return launch_k<KIND, OP_LAP>(st, order, color, rmode, L, blocks, nc, nf);
+}
+
+template <int OP, bool MIXED>
+hipError_t launch_tail_t(hipStream_t st, int order, int rmode, const TailList *T, int blocks,
+                         int nu1, int nu2, int nu0, unsigned long long *nc, unsigned long long *nf)
+{
+    const dim3 grid(blocks), block(kTailThreads);
+    if (order == 0) {
+        if (rmode == 0)
+            hipLaunchKernelGGL((k_tail<OP, MIXED, 0, 0>), grid, block, 0, st, T, nu1, nu2, nu0, nc,
+                               nf);
+        else
+            hipLaunchKernelGGL((k_tail<OP, MIXED, 0, 1>), grid, block, 0, st, T, nu1, nu2, nu0, nc,
+                               nf);
+    } else {
+        if (rmode == 0)
+            hipLaunchKernelGGL((k_tail<OP, MIXED, 1, 0>), grid, block, 0, st, T, nu1, nu2, nu0, nc,
+                               nf);
+        else
+            hipLaunchKernelGGL((k_tail<OP, MIXED, 1, 1>), grid, block, 0, st, T, nu1, nu2, nu0, nc,
+                               nf);
+    }
+    return hipGetLastError();
 }
 
 size_t npts_sz(int n) { return npts(n); }
@@ -378,37 +570,40 @@ void item_dims(int kind, int order, int n, int *gx, int *gy, int *gz)
 }
 
 hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color, int rmode,
-                          const BatchList *L, unsigned long long *nc, unsigned long long *nf)
+                          const BatchList *L, int blocks, unsigned long long *nc,
+                          unsigned long long *nf)
 {
+    if (blocks <= 0 || blocks % 8 != 0)
+        return hipErrorInvalidValue;
     // kinds whose arithmetic does not depend on op / order / rmode use one
     // instantiation
     switch (kind) {
     case LK_SWEEP:
-        return launch_kind<LK_SWEEP>(st, op, order, color, 0, L, nc, nf);
+        return launch_kind<LK_SWEEP>(st, op, order, color, 0, L, blocks, nc, nf);
     case LK_RESIDUAL:
-        return launch_kind<LK_RESIDUAL>(st, op, 0, 0, 0, L, nc, nf);
+        return launch_kind<LK_RESIDUAL>(st, op, 0, 0, 0, L, blocks, nc, nf);
     case LK_NORM:
-        return launch_kind<LK_NORM>(st, op, 0, 0, 0, L, nc, nf);
+        return launch_kind<LK_NORM>(st, op, 0, 0, 0, L, blocks, nc, nf);
     case LK_RESTRICT:
-        return launch_kind<LK_RESTRICT>(st, op, 0, 0, rmode, L, nc, nf);
+        return launch_kind<LK_RESTRICT>(st, op, 0, 0, rmode, L, blocks, nc, nf);
     case LK_PROLONG:
-        return launch_k<LK_PROLONG, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_PROLONG, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_MSWEEP:
-        return launch_k<LK_MSWEEP, OP_MA>(st, order, color, 0, L, nc, nf);
+        return launch_k<LK_MSWEEP, OP_MA>(st, order, color, 0, L, blocks, nc, nf);
     case LK_MRESIDUAL:
-        return launch_k<LK_MRESIDUAL, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_MRESIDUAL, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_MRESTRICT:
-        return launch_k<LK_MRESTRICT, OP_MA>(st, 0, 0, rmode, L, nc, nf);
+        return launch_k<LK_MRESTRICT, OP_MA>(st, 0, 0, rmode, L, blocks, nc, nf);
     case LK_MPROLONG:
-        return launch_k<LK_MPROLONG, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_MPROLONG, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_INJECT:
-        return launch_k<LK_INJECT, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_INJECT, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_ACCUM:
-        return launch_k<LK_ACCUM, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_ACCUM, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_ZERO:
-        return launch_k<LK_ZERO, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_ZERO, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     case LK_RES32:
-        return launch_k<LK_RES32, OP_MA>(st, 0, 0, 0, L, nc, nf);
+        return launch_k<LK_RES32, OP_MA>(st, 0, 0, 0, L, blocks, nc, nf);
     default:
         return hipErrorInvalidValue;
     }
@@ -417,8 +612,26 @@ hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *L, const double *partials,
                                  double *out)
 {
-    hipLaunchKernelGGL(k_batched_reduce, dim3(kMaxGrids), dim3(256), 0, st, L, partials, out);
+    hipLaunchKernelGGL(k_batched_reduce, dim3(kMaxGrids), dim3(1024), 0, st, L, partials, out);
     return hipGetLastError();
+}
+
+hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const TailList *T,
+                       int blocks, int nu1, int nu2, int nu0, unsigned long long *nc,
+                       unsigned long long *nf)
+{
+    if (blocks <= 0 || blocks > kMaxGrids)
+        return hipErrorInvalidValue;
+    switch (mode) {
+    case Engine::MODE_MA:
+        return launch_tail_t<OP_MA, false>(st, order, rmode, T, blocks, nu1, nu2, nu0, nc, nf);
+    case Engine::MODE_LAP:
+        return launch_tail_t<OP_LAP, false>(st, order, rmode, T, blocks, nu1, nu2, nu0, nc, nf);
+    case Engine::MODE_MIXED:
+        return launch_tail_t<OP_MA, true>(st, order, rmode, T, blocks, nu1, nu2, nu0, nc, nf);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -455,10 +668,8 @@ void Engine::drop_graphs()
             if (x)
                 (void)hipGraphExecDestroy(x);
         gseg_[m].clear();
-        graph_D_[m] = -1;
+        graph_shape_[m].clear();
         graph_dl_[m] = nullptr;
-        graph_stride_[m] = 0;
-        graph_nl_[m] = 0;
     }
 }
 
@@ -485,17 +696,18 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
             p0 = &p;
         else if (p.nu1 != p0->nu1 || p.nu2 != p0->nu2 || p.nu0 != p0->nu0 || p.order != p0->order ||
                  p.restriction != p0->restriction || p.precision != p0->precision ||
-                 p.inner_cycles != p0->inner_cycles)
+                 p.inner_cycles != p0->inner_cycles || p.coarse_n != p0->coarse_n ||
+                 p.max_blocks != p0->max_blocks)
             return fail(MA_ERR_ARG,
                         "solvers in one batch must share smoothing counts, ordering, "
-                        "restriction and precision");
+                        "restriction, precision, inner cycles, coarse_n and max_blocks");
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
-    // A captured tick reads the grids' operand pointers from the device lists,
-    // which every rebuild rewrites; what it holds as plain kernel arguments
-    // is the partials buffer and, on the fused path, the grids themselves.
-    // A change of either invalidates the graphs.
+    // A captured tick reads the grids' operand pointers from the device
+    // tables, which every rebuild rewrites; what it holds as plain kernel
+    // arguments is the partials buffer and, on the fused path, the grids
+    // themselves.  A change of either invalidates the graphs.
     const bool fused = solves.size() == 1 && p0->smoother == MA_SMOOTHER_FUSED &&
                        p0->order == MA_COLOR4;
     bool same = solves.size() == solves_.size();
@@ -515,6 +727,8 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     rmode_ = p0->restriction == MA_RESTRICT_HALF ? 1 : 0;
     inner_ = p0->inner_cycles;
     mixed_ = p0->precision == MA_MIXED;
+    coarse_n_ = p0->coarse_n;
+    max_blocks_ = p0->max_blocks > 0 ? p0->max_blocks : kDefaultMaxBlocks;
     fused_ = fused;
     built_ = false;
     if (!stream_) {
@@ -568,6 +782,17 @@ ma_status Engine::read_counters(std::vector<unsigned long long> &nonconvex,
     nonconvex.assign(hcount_, hcount_ + solves_.size());
     fallbacks.assign(hcount_ + kMaxGrids, hcount_ + kMaxGrids + solves_.size());
     return MA_OK;
+}
+
+int Engine::levels(int i) const { return int(solves_[i].s->lv.size()); }
+
+int Engine::multiblock_levels(int i) const
+{
+    const ma_solver *s = solves_[i].s;
+    int m = 0;
+    while (m < int(s->lv.size()) && s->lv[m].n > coarse_n_)
+        ++m;
+    return m;
 }
 
 const double *Engine::level_u(int i, int l, Mode mode) const
@@ -671,38 +896,52 @@ GridItem Engine::grid(int kind, int i, int l, Mode mode) const
     return G;
 }
 
+// Builds the device tables of one tick of mode over the active solves.  A
+// list's launch size comes from ALL solves of the engine (active or not), so
+// it does not change when solves pause or finish, and neither does a
+// captured graph that replays it.
 ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
 {
     hbuf_.clear();
     loff_.clear();
     lng_.clear();
+    lgrid_.clear();
     stride_ = list_bytes(int(solves_.size()));
     const int S = int(solves_.size());
     auto on = [&](int i) { return solves_[i].s && active[i]; };
-    auto levels = [&](int i) { return int(solves_[i].s->lv.size()); };
-    D_ = 0;
+    D_ = Dall_ = 0;
     for (int i = 0; i < S; ++i)
-        if (on(i))
-            D_ = std::max(D_, levels(i));
+        if (on(i)) {
+            D_ = std::max(D_, multiblock_levels(i));
+            Dall_ = std::max(Dall_, levels(i));
+        }
     const bool mixed = mode == MODE_MIXED;
     bool overflow = false;
     int pnext = 0;
-    auto make = [&](int kind, int d, auto pred, bool partial) {
+    // A list of kind at depth d over the solves for which pred holds and
+    // which have a level d: a multi-block level when mb is set, any level
+    // otherwise.
+    auto make = [&](int kind, int d, bool mb, auto pred, bool partial) {
         BatchList L;
         L.ngrids = 0;
         L.total = 0;
         L.pad[0] = L.pad[1] = 0;
         int start = 0;
+        long bound = 0;
         for (int i = 0; i < S; ++i) {
-            if (!on(i) || levels(i) <= d || !pred(i))
+            if (!solves_[i].s || (mb ? multiblock_levels(i) : levels(i)) <= d || !pred(i))
+                continue;
+            int gx, gy, gz;
+            const int n = mixed ? solves_[i].s->mx[d].n : solves_[i].s->lv[d].n;
+            item_dims(kind, order_, n, &gx, &gy, &gz);
+            bound += long(gx) * gy * gz;
+            if (!active[i])
                 continue;
             if (L.ngrids == kMaxGrids) {
                 overflow = true;
                 break;
             }
             GridItem G = grid(kind, i, d, mode);
-            int gx, gy, gz;
-            item_dims(kind, order_, G.n, &gx, &gy, &gz);
             G.gx = gx;
             G.gy = gy;
             G.start = start;
@@ -715,11 +954,12 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         }
         L.total = start;
         // every list sits at index * stride_, so a list's device address
-        // depends only on its index: graphs captured for one composition
-        // stay valid when solves join or leave (same depth, same slots)
+        // depends only on its index
         const size_t off = loff_.size() * stride_;
         loff_.push_back(off);
         lng_.push_back(L.ngrids);
+        const long b8 = ((bound + 7) / 8) * 8;
+        lgrid_.push_back(bound == 0 ? 0 : int(std::min<long>(b8, max_blocks_)));
         hbuf_.resize(off + stride_, 0);
         std::memcpy(hbuf_.data() + off, &L, list_bytes(L.ngrids));
         return int(loff_.size()) - 1;
@@ -730,50 +970,89 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
     res_.assign(D_, -1);
     rst_.assign(D_, -1);
     pro_.assign(D_, -1);
-    inj_.assign(D_, -1);
+    inj_.assign(std::max(Dall_ - 1, 0), -1);
     const int SW = mixed ? LK_MSWEEP : LK_SWEEP;
     for (int d = 0; d < D_; ++d) {
         for (int k = 0; k < ksw; ++k)
-            swd_[d].push_back(make(SW, d, [&](int i) {
+            swd_[d].push_back(make(SW, d, true, [&](int i) {
                 const int cnt = d < levels(i) - 1 ? nu1_ : nu0_;
                 return cnt > k;
             }, false));
-        if (d < D_ - 1) {
-            auto nc = [&](int i) { return d < levels(i) - 1; };
-            res_[d] = make(mixed ? LK_MRESIDUAL : LK_RESIDUAL, d, nc, false);
-            rst_[d] = make(mixed ? LK_MRESTRICT : LK_RESTRICT, d, nc, false);
-            pro_[d] = make(mixed ? LK_MPROLONG : LK_PROLONG, d, nc, false);
-            if (mixed)
-                inj_[d] = make(LK_INJECT, d, nc, false);
-        }
+        auto nc = [&](int i) { return d < levels(i) - 1; };
+        res_[d] = make(mixed ? LK_MRESIDUAL : LK_RESIDUAL, d, true, nc, false);
+        rst_[d] = make(mixed ? LK_MRESTRICT : LK_RESTRICT, d, true, nc, false);
+        pro_[d] = make(mixed ? LK_MPROLONG : LK_PROLONG, d, true, nc, false);
         for (int k = 0; k < nu2_; ++k)
-            swu_[d].push_back(make(SW, d, [&](int i) { return d < levels(i) - 1; }, false));
+            swu_[d].push_back(make(SW, d, true, nc, false));
     }
+    if (mixed)
+        for (int d = 0; d + 1 < Dall_; ++d)
+            inj_[d] = make(LK_INJECT, d, false, [&](int i) { return d < levels(i) - 1; }, false);
     auto all = [](int) { return true; };
-    norm_ = make(mixed ? LK_RES32 : LK_NORM, 0, all, true);
+    norm_ = make(mixed ? LK_RES32 : LK_NORM, 0, false, all, true);
     accum_ = zero_ = -1;
     if (mixed) {
-        accum_ = make(LK_ACCUM, 0, all, false);
-        zero_ = make(LK_ZERO, 0, all, false);
+        accum_ = make(LK_ACCUM, 0, false, all, false);
+        zero_ = make(LK_ZERO, 0, false, all, false);
     }
     if (overflow)
         return fail(MA_ERR_ARG, "too many grids in one batched launch");
     if (size_t(pnext) > partials_cap_)
         return fail(MA_ERR_ARG, "partial-sum buffer too small for the batch");
+
+    // coarse-level table, after the lists
+    toff_ = hbuf_.size();
+    hbuf_.resize(toff_ + tail_bytes(S), 0);
+    {
+        TailList *T = reinterpret_cast<TailList *>(hbuf_.data() + toff_);
+        int nt = 0, bound = 0;
+        for (int i = 0; i < S; ++i) {
+            if (!solves_[i].s)
+                continue;
+            const int m = multiblock_levels(i), L = levels(i);
+            if (L - m <= 0)
+                continue;
+            if (L - m > kMaxTail)
+                return fail(MA_ERR_ARG, "too many coarse levels for the coarse-level kernel");
+            ++bound;
+            if (!active[i])
+                continue;
+            TailEntry &E = T->e[nt++];
+            E.nlev = L - m;
+            for (int l = 0; l < L - m; ++l) {
+                const int d = m + l;
+                TailLevel &V = E.lv[l];
+                V.sw = grid(mixed ? LK_MSWEEP : LK_SWEEP, i, d, mode);
+                if (d < L - 1) {
+                    V.res = grid(mixed ? LK_MRESIDUAL : LK_RESIDUAL, i, d, mode);
+                    V.rst = grid(mixed ? LK_MRESTRICT : LK_RESTRICT, i, d, mode);
+                    V.pro = grid(mixed ? LK_MPROLONG : LK_PROLONG, i, d, mode);
+                }
+            }
+        }
+        T->nsolves = nt;
+        tail_blocks_ = bound;
+    }
+
     prof_bytes_tick_ = 0.0;
     prof_launches_tick_ = 0;
     for (int i = 0; i < S; ++i)
-        if (on(i)) {
+        if (on(i) && multiblock_levels(i) > 0) {
             const double in = interior(mixed ? solves_[i].s->mx[0].n : solves_[i].s->lv[0].n);
             const bool single = levels(i) == 1;
             const int sweeps = single ? nu0_ : nu1_ + nu2_;
             const int reps = mixed ? inner_ : 1;
             prof_bytes_tick_ += reps * sweeps * (mixed ? 20.0 : 24.0) * in;
         }
-    {
+    if (D_ > 0) {
         const int reps = mixed ? inner_ : 1;
         const int colours = order_ == 1 ? 8 : 4;
-        prof_launches_tick_ = reps * colours * (ksw + (D_ > 1 ? nu2_ : 0));
+        int launches = 0;
+        for (int idx : swd_[0])
+            launches += lgrid_[idx] > 0 ? colours : 0;
+        for (int idx : swu_[0])
+            launches += lgrid_[idx] > 0 ? colours : 0;
+        prof_launches_tick_ = reps * launches;
     }
     built_mode_ = mode;
     built_active_ = active;
@@ -835,7 +1114,10 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
     const int colours = order_ == 1 ? 8 : 4;
     auto L = [&](int idx) { return reinterpret_cast<const BatchList *>(dl_ + loff_[idx]); };
     auto go = [&](int kind, int idx, int color) -> ma_status {
-        E_HIP(launch_batched(stream_, kind, op, order_, color, rmode_, L(idx), dcount_, dfall_));
+        if (lgrid_[idx] == 0)
+            return MA_OK;
+        E_HIP(launch_batched(stream_, kind, op, order_, color, rmode_, L(idx), lgrid_[idx], dcount_,
+                             dfall_));
         return MA_OK;
     };
     const int SW = mixed ? LK_MSWEEP : LK_SWEEP;
@@ -878,12 +1160,14 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
             MA_TRY(sweeps(swd_[d], d));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
-            if (d < D_ - 1) {
-                MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
-                MA_TRY(go(mixed ? LK_MRESTRICT : LK_RESTRICT, rst_[d], 0));
-            }
+            MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
+            MA_TRY(go(mixed ? LK_MRESTRICT : LK_RESTRICT, rst_[d], 0));
         }
-        for (int d = D_ - 2; d >= 0; --d) {
+        if (tail_blocks_ > 0)
+            E_HIP(launch_tail(stream_, int(mode), order_, rmode_,
+                              reinterpret_cast<const TailList *>(dl_ + toff_), tail_blocks_, nu1_,
+                              nu2_, nu0_, dcount_, dfall_));
+        for (int d = D_ - 1; d >= 0; --d) {
             MA_TRY(go(mixed ? LK_MPROLONG : LK_PROLONG, pro_[d], 0));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
@@ -895,7 +1179,7 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
     };
     if (cycle) {
         if (mixed) {
-            for (int d = 0; d + 1 < D_; ++d)
+            for (int d = 0; d + 1 < Dall_; ++d)
                 MA_TRY(go(LK_INJECT, inj_[d], 0));
             MA_TRY(go(LK_ZERO, zero_, 0));
             for (int it = 0; it < inner_; ++it)
@@ -910,6 +1194,21 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
     return MA_OK;
 }
 
+// The launch shapes baked into a captured tick.
+std::vector<int> Engine::shape() const
+{
+    std::vector<int> s;
+    s.reserve(lgrid_.size() + 8);
+    s.push_back(D_);
+    s.push_back(Dall_);
+    s.push_back(int(stride_));
+    s.push_back(int(toff_));
+    s.push_back(tail_blocks_);
+    s.push_back(int(loff_.size()));
+    s.insert(s.end(), lgrid_.begin(), lgrid_.end());
+    return s;
+}
+
 ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
                       std::vector<double> &norms)
 {
@@ -922,8 +1221,7 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
     const int m = int(mode) + (profile_ ? 3 : 0);
     size_t nev = 0;
     if (cycle && graphs_) {
-        if (gseg_[m].empty() || graph_D_[m] != D_ || graph_dl_[m] != dl_ ||
-            graph_stride_[m] != stride_ || graph_nl_[m] != loff_.size())
+        if (gseg_[m].empty() || graph_dl_[m] != dl_ || graph_shape_[m] != shape())
             MA_TRY(capture(m, mode));
         // segment k is followed by timing event k (profiled form only)
         const size_t ns = gseg_[m].size();
@@ -975,6 +1273,8 @@ ma_status Engine::capture(int m, Mode mode)
         if (x)
             (void)hipGraphExecDestroy(x);
     gseg_[m].clear();
+    graph_shape_[m].clear();
+    graph_dl_[m] = nullptr;
     seg_tmp_.clear();
     pev_used_ = 0;
     seg_capture_ = profile_;
@@ -990,12 +1290,15 @@ ma_status Engine::capture(int m, Mode mode)
             (void)hipGraphDestroy(g);
         seg_tmp_.clear();
     };
-    if (st != MA_OK || ec != hipSuccess) {
-        release();
+    auto drop = [&]() {
         for (hipGraphExec_t x : gseg_[m])
             if (x)
                 (void)hipGraphExecDestroy(x);
         gseg_[m].clear();
+    };
+    if (st != MA_OK || ec != hipSuccess) {
+        release();
+        drop();
         if (st != MA_OK)
             return st;
         return fail(MA_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
@@ -1008,19 +1311,14 @@ ma_status Engine::capture(int m, Mode mode)
             e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             release();
-            for (hipGraphExec_t y : gseg_[m])
-                if (y)
-                    (void)hipGraphExecDestroy(y);
-            gseg_[m].clear();
+            drop();
             return fail(MA_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
         gseg_[m].push_back(x);
     }
     release();
-    graph_D_[m] = D_;
+    graph_shape_[m] = shape();
     graph_dl_[m] = dl_;
-    graph_stride_[m] = stride_;
-    graph_nl_[m] = loff_.size();
     return MA_OK;
 }
 

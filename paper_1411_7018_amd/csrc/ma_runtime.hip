@@ -59,6 +59,14 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "cycle counts must be >= 0 and 1 <= inner_cycles <= 16";
         return false;
     }
+    if (p->coarse_n < 0 || p->coarse_n > 32) {
+        why = "coarse_n must be in 0..32";
+        return false;
+    }
+    if (p->max_blocks < 0 || p->max_blocks % 8 != 0 || p->max_blocks > (1 << 20)) {
+        why = "max_blocks must be 0 or a multiple of 8 up to 2^20";
+        return false;
+    }
     if (p->graphs != 0 && p->graphs != 1) {
         why = "graphs must be 0 or 1";
         return false;
@@ -121,6 +129,8 @@ void ma_params_default(ma_params *p, int n)
     p->init_max_cycles = 30;
     p->inner_cycles = 2;
     p->graphs = 1;
+    p->coarse_n = 16;
+    p->max_blocks = 0;
 }
 
 int ma_levels(int n, int *ns, int cap)
