@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the FAS multigrid Monge-Ampere solver on one MI355X.
 
-One step = one complete solve of the 129^3 seeded quadratic problem
-(u = x^T A x / 2 + b^T x, A SPD with eigenvalues in [0.5, 2], f = det A):
-Poisson initial guess, then FAS V(2,2) cycles until the relative discrete L2
-residual is <= 1e-8, with every input resident in HBM before timing starts.
-Prints one JSON line: solves/s (value), p50/p99 latency, grid-point updates/s,
-the smoother's algorithmic bandwidth against the HBM peak, and the CPU oracle
-timed on a bounded sample of the same workload.
+Default workload (one step = one complete solve): the 129^3 seeded quadratic
+problem (u = x^T A x / 2 + b^T x, A SPD with eigenvalues in [0.5, 2],
+f = det A): Poisson initial guess, then FAS V(2,2) cycles until the relative
+discrete L2 residual is <= 1e-8, every input resident in HBM before timing
+starts.  Other workloads:
+  example4_17, expcos257, expcos385   single solves of other sizes;
+  batch64   64 seeded solves (sizes 33^3..129^3, quadratic or exp-cos) run
+            as one batch; one step = the whole batch;
+  served    a Poisson-arrival stream of requests (65^3..385^3) through the
+            continuous-batching server; --steps requests.
+Before timing, the autotuner picks the engine's launch shapes on the same
+solvers and data (outside the timed region; --no-tune keeps the defaults).
+
+Prints one JSON line: solves/s (value), p50/p99 latency, grid-point
+updates/s, the finest-level smoother's algorithmic bandwidth against the HBM
+peak (HIP events around its launches inside the timed region), and, for the
+default run, the CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -23,25 +33,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = {
+METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
+SINGLE = {
     # name: (kind, n, seed, tol)
     "quadratic129": ("quadratic", 128, 1001, 1e-8),
     "example4_17": ("example4", 16, 0, 1e-10),
     "expcos257": ("exp_cos", 256, 3001, 1e-8),
     "expcos385": ("exp_cos", 384, 5001, 1e-8),
 }
+WORKLOADS = sorted(SINGLE) + ["batch64", "served"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="quadratic129", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--smoother", default="auto", choices=["auto", "color", "fused"])
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (served: requests); default per workload")
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="quadratic129", choices=WORKLOADS)
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64, except batch64 (mixed)")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=None, help="served: HBM budget")
     return ap.parse_args()
+
+
+def roofline(reps):
+    sec = sum(r["smooth_seconds"] for r in reps)
+    by = sum(r["smooth_bytes"] for r in reps)
+    la = sum(r["smooth_launches"] for r in reps)
+    ach = by / sec / 1e9 if sec > 0 else 0.0
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_batched sweep, finest level (24 B per interior node per sweep)",
+            "avg_launch_us": 1e6 * sec / max(la, 1), "launches": la}
 
 
 def cpu_baseline(kind, n, seed, tol):
@@ -60,7 +87,6 @@ def cpu_baseline(kind, n, seed, tol):
                 "sample": f"one full solve of the same {n + 1}^3 problem "
                           f"({rep.init_cycles} Poisson + {rep.cycles} FAS V(2,2) cycles, "
                           f"{dt:.1f} s)"}
-    # large grids: time V-cycles and scale by the GPU's cycle count
     oracle.poisson_init(u, p.f, oracle.params())
     t0 = time.perf_counter()
     cyc = 0
@@ -72,79 +98,191 @@ def cpu_baseline(kind, n, seed, tol):
             "sample": f"{cyc} FAS V(2,2) cycles on the same {n + 1}^3 problem"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(a multi-GPU layout is described in the design notes)"}))
-        sys.exit(2)
+def base_line(args, value, steps, warmup, elapsed, lat, precision):
+    return {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1e3 * elapsed / max(steps, 1),
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == "fp64" else "f32+f64", "data": "synthetic",
+    }
+
+
+def tune_note(choice):
+    if choice is None:
+        return None
+    return {"coarse_n": choice.coarse_n, "max_blocks": choice.max_blocks,
+            "ms_per_tick": 1e3 * choice.seconds_per_tick}
+
+
+def run_single(args, precision):
     import torch
 
-    from paper_1411_7018_amd import Solver, problems as P
+    from paper_1411_7018_amd import Solver, autotune, problems as P
 
-    kind, n, seed, tol = WORKLOADS[args.workload]
+    kind, n, seed, tol = SINGLE[args.workload]
+    steps = args.steps or 20
+    warmup = 3 if args.warmup is None else args.warmup
     prob = P.make(kind, n, seed)
     dev = torch.device("cuda:0")
     u_init = torch.from_numpy(P.initial_guess(prob)).to(dev)
     f = torch.from_numpy(prob.f).to(dev)
     u = torch.empty_like(u_init)
-    s = Solver(n, precision=args.precision, smoother=args.smoother, profile=1)
+    s = Solver(n, precision=precision, profile=1)
+    choice = None
+    if not args.no_tune:
+        choice = autotune.tune([s], [u_init], [f])
 
     def step():
         u.copy_(u_init)
         return s.solve(u, f, tol=tol)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     lat, reps = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         reps.append(step())
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-
-    value = args.steps / elapsed
     last = reps[-1]
-    sm_bytes = sum(r["smooth_bytes"] for r in reps)
-    sm_sec = sum(r["smooth_seconds"] for r in reps)
-    sm_launch = sum(r["smooth_launches"] for r in reps)
-    achieved = sm_bytes / sm_sec / 1e9 if sm_sec > 0 else 0.0
-    updates = sum(r["point_updates"] for r in reps)
     err = float(np.abs(u.cpu().numpy() - prob.u_exact).max())
-    out = {
-        "metric": "solves/s at 1e-8 relative residual (p50/p99 latency; smoother GB/s vs HBM peak)",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
-        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"{kind} {n + 1}^3 single solve, seed {seed}, tol {tol:g}, "
-                               f"Poisson initial guess, FAS V(2,2), 4-colour GS",
-                   "n": n, "tol": tol, "precision": args.precision, "smoother": args.smoother},
-        "updates_per_s": updates / elapsed,
-        "cycles": last["cycles"],
-        "init_cycles": last["init_cycles"],
-        "rel_res": last["rel_res"],
-        "max_err_vs_exact": err,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "finest-level smoother (one sweep = 24 B per interior node)",
-                     "avg_launch_us": 1e6 * sm_sec / max(sm_launch, 1),
-                     "launches": sm_launch},
-    }
+    out = base_line(args, steps / elapsed, steps, warmup, elapsed, lat, precision)
+    out["config"] = {
+        "workload": f"{kind} {n + 1}^3 single solve, seed {seed}, tol {tol:g}, Poisson "
+                    f"initial guess, FAS V(2,2), 4-colour nonlinear GS, {precision}",
+        "n": n, "tol": tol, "precision": precision, "tuned": tune_note(choice)}
+    out.update({"updates_per_s": sum(r["point_updates"] for r in reps) / elapsed,
+                "cycles": last["cycles"], "init_cycles": last["init_cycles"],
+                "rel_res": last["rel_res"], "max_err_vs_exact": err,
+                "roofline": roofline(reps)})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(kind, n, seed, tol)
+    return out
+
+
+def run_batch(args, precision):
+    import torch
+
+    from paper_1411_7018_amd import Solver, autotune, problems as P
+    from paper_1411_7018_amd.batch import solve_batch
+
+    steps = args.steps or 5
+    warmup = 1 if args.warmup is None else args.warmup
+    specs = P.batch_specs(64)
+    data = [P.make_device(k, n, sd) for k, n, sd in specs]
+    us0 = [d[0] for d in data]
+    fs = [d[1] for d in data]
+    us = [torch.empty_like(u) for u in us0]
+    solvers = [Solver(n, precision=precision, profile=1) for _, n, _ in specs]
+    choice = None
+    if not args.no_tune:
+        choice = autotune.tune(solvers, us0, fs, ticks=3)
+
+    def step():
+        for u, u0 in zip(us, us0):
+            u.copy_(u0)
+        st, reps = solve_batch(solvers, us, fs, tol=1e-8)
+        if st != 0:
+            raise RuntimeError(f"batch status {st}")
+        return reps
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, allreps = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        allreps.append(step())
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nsol = len(specs)
+    out = base_line(args, steps * nsol / elapsed, steps, warmup, elapsed, lat, precision)
+    pts = sum((n + 1) ** 3 for _, n, _ in specs)
+    out["config"] = {
+        "workload": f"batch of {nsol} seeded solves (sizes 33^3..129^3, quadratic or "
+                    f"exp-cos, {pts / 1e6:.1f}M grid points), tol 1e-8, Poisson initial "
+                    f"guess, FAS V(2,2), {precision}, one launch per level phase",
+        "solves": nsol, "tol": 1e-8, "precision": precision, "tuned": tune_note(choice),
+        "latency": "per batch step"}
+    # smooth_* of a batch report are the whole batch's totals: use one per step
+    out.update({"updates_per_s": sum(r["point_updates"] for reps in allreps for r in reps)
+                / elapsed,
+                "max_cycles": max(r["cycles"] for r in allreps[-1]),
+                "max_rel_res": max(r["rel_res"] for r in allreps[-1]),
+                "roofline": roofline([reps[0] for reps in allreps])})
+    return out
+
+
+def run_served(args, precision):
+    import torch
+
+    from paper_1411_7018_amd import Solver, problems as P
+    from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
+
+    count = args.steps or 256
+    warmup = 8 if args.warmup is None else args.warmup
+    rate = args.rate
+    if rate is None:
+        # 0.8 x the plain FP64 capacity: mean solo service time over the size mix
+        tsvc = 0.0
+        for n, w in zip(P.SERVE_SIZES, P.SERVE_WEIGHTS):
+            u, f = P.make_device("exp_cos", n, 11)
+            s = Solver(n)
+            s.solve(u.clone(), f)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve(u, f)
+            torch.cuda.synchronize()
+            tsvc += w * (time.perf_counter() - t0)
+            del s, u, f
+        rate = 0.8 / tsvc
+    budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else GpuBackend.budget_default()
+    be = GpuBackend(precision=precision, tol=1e-8, max_slots=64)
+    if warmup:
+        Server(be, budget).run(requests_from_trace(P.arrival_trace(warmup, rate, seed=4999)))
+    torch.cuda.synchronize()
+    reqs = requests_from_trace(P.arrival_trace(count, rate, seed=5000))
+    srv = Server(be, budget, max_slots=64)
+    t0 = time.perf_counter()
+    st = srv.run(reqs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = [r.latency for r in reqs if r.status == 0]
+    out = base_line(args, st.solves_per_s, count, warmup, elapsed, lat, precision)
+    out["config"] = {
+        "workload": f"served stream: {count} Poisson arrivals at {rate:.1f}/s, sizes "
+                    f"65^3/129^3/257^3/385^3 (p=.4/.3/.2/.1), quadratic or exp-cos, tol 1e-8, "
+                    f"{precision}, HBM budget {budget / 2**30:.1f} GiB, continuous batching",
+        "requests": count, "rate_per_s": rate, "budget_bytes": budget, "precision": precision,
+        "latency": "completion - arrival"}
+    out.update({"completed": st.completed, "rejected": st.rejected,
+                "mean_live": st.mean_live, "max_live": st.max_live, "queued": st.queued,
+                "peak_bytes": st.peak_bytes, "ticks": st.ticks,
+                "updates_per_s": sum(r.report["point_updates"] for r in reqs if r.report)
+                / st.makespan})
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (the "
+                                   "multi-GPU layout is documented as a design only)"}))
+        sys.exit(2)
+    precision = args.precision or ("mixed" if args.workload == "batch64" else "fp64")
+    if args.workload in SINGLE:
+        out = run_single(args, precision)
+    elif args.workload == "batch64":
+        out = run_batch(args, precision)
+    else:
+        out = run_served(args, precision)
     print(json.dumps(out), flush=True)
 
 

@@ -142,6 +142,12 @@ const char *ma_last_error(const ma_solver *s);
 /* Order later work on another hipStream_t. */
 ma_status ma_set_stream(ma_solver *s, void *hip_stream);
 
+/* Change the launch shape of later cycles without touching the hierarchy:
+ * coarse_n and max_blocks as in ma_params (the autotuner's knobs).  The
+ * arithmetic, and so every result, is the same for every value.
+ * Errors: MA_ERR_ARG for values outside their ranges (nothing changes). */
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks);
+
 /* Solve det(D^2 u) = f (Algorithm 1 repeated under the stopping rule of
  * Section 4): run V(nu1,nu2) cycles until the discrete L2 residual is
  * <= tol * res0 (tol <= 0 selects params.tol), res0 being the residual of
@@ -194,11 +200,16 @@ ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_
 /* together, one launch per level phase for all of them.                    */
 /* ---------------------------------------------------------------------- */
 
-/* Solve count independent problems together.  solvers[i] must have been
- * created for the size of u[i], f[i] and all with the same precision,
- * ordering and smoothing counts.  Each result equals that of ma_solve on
- * the same solver alone.  reps (may be NULL) receives count reports.  Returns
- * the first non-OK status over the solves (all solves still complete). */
+/* Solve count independent problems together (up to 64 per engine pass;
+ * larger counts run in consecutive groups of 64).  solvers[i] must have
+ * been created for the size of u[i], f[i] and all with the same precision,
+ * ordering, smoothing counts, inner_cycles, coarse_n and max_blocks
+ * (else MA_ERR_ARG).  Each result equals that of ma_solve on the same
+ * solver alone.  reps (may be NULL) receives count reports; when the first
+ * solver of a group has profile set, the smooth_* fields of every report of
+ * that group hold the group's totals (finest-level smoothing of all its
+ * solves together).  Returns the first non-OK status over the solves (all
+ * solves still complete).  Synchronises the first solver's stream. */
 ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const double *const *f,
                          int count, double tol, unsigned flags, ma_report *reps);
 

@@ -80,6 +80,7 @@ _L.ma_destroy.restype = None
 _L.ma_last_error.argtypes = [_vp]
 _L.ma_last_error.restype = ctypes.c_char_p
 _L.ma_set_stream.argtypes = [_vp, _vp]
+_L.ma_retune.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
 _L.ma_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_vcycle.argtypes = [_vp, _vp, _vp]
 _L.ma_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
@@ -99,14 +100,14 @@ _L.ma_batch_add.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_uint,
 _L.ma_batch_tick.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _L.ma_batch_report.argtypes = [_vp, ctypes.c_int, _R]
 _L.ma_batch_remove.argtypes = [_vp, ctypes.c_int]
-for _name in ("ma_create", "ma_set_stream", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
+for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
               "ma_restrict", "ma_prolong_correct", "ma_poisson_init", "ma_solve_batch",
               "ma_batch_create", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
               "ma_batch_remove"):
     getattr(_L, _name).restype = ctypes.c_int
 
 EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", "ma_destroy",
-           "ma_last_error", "ma_set_stream", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
+           "ma_last_error", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
            "ma_restrict", "ma_prolong_correct", "ma_poisson_init", "ma_solve_batch",
            "ma_batch_create", "ma_batch_destroy", "ma_batch_last_error", "ma_batch_add",
            "ma_batch_tick", "ma_batch_report", "ma_batch_remove")
@@ -157,6 +158,10 @@ def ma_last_error(h: int | None) -> str:
 
 def ma_set_stream(h: int, stream: int | None) -> None:
     _check(_L.ma_set_stream(h, stream or None), h)
+
+
+def ma_retune(h: int, coarse_n: int, max_blocks: int) -> None:
+    _check(_L.ma_retune(h, int(coarse_n), int(max_blocks)), h)
 
 
 def ma_solve(h: int, u: int, f: int, tol: float, flags: int) -> ma_report:

@@ -1,0 +1,117 @@
+"""Autotuner for the launch shapes of the batched engine.
+
+The engine's arithmetic is fixed; what changes its speed is how the work is
+cut into launches:
+  * ``max_blocks`` -- the cap on the blocks of one row-kernel launch.  Few
+    blocks walk many rows each inside one XCD's window (good L2 reuse of the
+    stencil halos on big grids); many blocks put more waves in flight (good
+    latency hiding on mid-size grids).
+  * ``coarse_n``   -- levels with n <= coarse_n run inside the
+    single-workgroup coarse-level kernel instead of one launch per phase.
+
+``tune`` times every candidate pair on the device, on the caller's own
+solvers and data (a copy of u), with one tick per candidate for graph
+capture followed by timed ticks, and leaves the solvers retuned to the
+fastest pair.  All candidates give bitwise the same results, so tuning never
+changes what a solve computes.  ``load`` / ``save`` keep choices in a JSON
+file keyed by device name, grid sizes and precision.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+import time
+
+import torch
+
+BLOCKS = (2048, 4096, 8192, 16384, 32768)
+COARSE = (0, 8, 16, 32)
+
+
+@dataclasses.dataclass
+class Choice:
+    coarse_n: int
+    max_blocks: int
+    seconds_per_tick: float
+    table: list          # [(coarse_n, max_blocks, seconds_per_tick), ...]
+
+    def as_dict(self) -> dict:
+        return {"coarse_n": self.coarse_n, "max_blocks": self.max_blocks,
+                "seconds_per_tick": self.seconds_per_tick,
+                "table": [list(r) for r in self.table]}
+
+
+def key(sizes, precision: str, order: str = "4c") -> str:
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{dev}|{precision}|{order}|" + ",".join(str(n) for n in sorted(sizes))
+
+
+def _time_ticks(solvers, us, fs, ticks: int) -> float:
+    from .batch import ResidentBatch
+
+    b = ResidentBatch(len(solvers))
+    try:
+        work = [u.clone() for u in us]
+        for s, u, f in zip(solvers, work, fs):
+            # start where a solve's FAS cycles start (after the Poisson
+            # guess); an unreachable tolerance keeps every solve cycling
+            s.poisson_init(u, f)
+            b.add(s, u, f, tol=1e-300, init_poisson=False)
+        b.tick()                       # entry residuals, first tick, capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ticks):
+            b.tick()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / ticks
+    finally:
+        b.close()
+
+
+def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE,
+         verbose: bool = False) -> Choice:
+    """Time each (coarse_n, max_blocks) pair on one batched tick of these
+    solves and retune the solvers to the fastest.  The solves must fit one
+    batch (at most 64, shared smoothing parameters)."""
+    if not solvers:
+        raise ValueError("nothing to tune")
+    if any(s.params.max_cycles < ticks + 1 for s in solvers):
+        raise ValueError("max_cycles must exceed the number of timed ticks")
+    table = []
+    for cn in coarse:
+        for mb in blocks:
+            for s in solvers:
+                s.retune(coarse_n=cn, max_blocks=mb)
+            t = min(_time_ticks(solvers, us, fs, ticks) for _ in range(2))
+            table.append((cn, mb, t))
+            if verbose:
+                print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d}: {1e3 * t:.3f} ms/tick",
+                      flush=True)
+    cn, mb, t = min(table, key=lambda r: r[2])
+    for s in solvers:
+        s.retune(coarse_n=cn, max_blocks=mb)
+    return Choice(cn, mb, t, table)
+
+
+def load(path: str, k: str) -> dict | None:
+    try:
+        with open(path) as fh:
+            return json.load(fh).get(k)
+    except (OSError, ValueError):
+        return None
+
+
+def save(path: str, k: str, choice: Choice) -> None:
+    data = {}
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        pass
+    data[k] = choice.as_dict()
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -68,7 +68,7 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
             refs[i].f = f[base + i];
         }
         ma_solver *s0 = solvers[base];
-        if (eng.set(refs, s0->stream, s0->p.graphs != 0, false) != MA_OK)
+        if (eng.set(refs, s0->stream, s0->p.graphs != 0, s0->p.profile != 0) != MA_OK)
             return s0->fail(MA_ERR_ARG, eng.error());
         std::vector<SolveState> st(m);
         std::vector<SolveState *> ptr(m);
@@ -90,9 +90,16 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
         std::vector<unsigned long long> nc, fb;
         if (eng.read_counters(nc, fb) != MA_OK)
             return s0->fail(MA_ERR_DEVICE, eng.error());
+        double psec = 0.0, pbytes = 0.0;
+        int plaunch = 0;
+        if (s0->p.profile)
+            eng.take_profile(&psec, &plaunch, &pbytes);
         const double t1 = now_seconds();
         for (int i = 0; i < m; ++i) {
             SolveState &x = st[i];
+            x.rep.smooth_seconds = psec;
+            x.rep.smooth_launches = plaunch;
+            x.rep.smooth_bytes = pbytes;
             x.rep.nonconvex = (long long)nc[i];
             x.rep.fp64_fallbacks = (long long)fb[i];
             x.rep.seconds = t1 - x.t0;

@@ -194,6 +194,20 @@ ma_status ma_set_stream(ma_solver *s, void *hip_stream)
     return MA_OK;
 }
 
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks)
+{
+    if (!s)
+        return MA_ERR_ARG;
+    ma_params q = s->p;
+    q.coarse_n = coarse_n;
+    q.max_blocks = max_blocks;
+    std::string why;
+    if (!valid_params(&q, why))
+        return s->fail(MA_ERR_ARG, why);
+    s->p = q;
+    return MA_OK;
+}
+
 ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigned flags,
                    ma_report *rep)
 {

@@ -31,7 +31,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "Problem", "grid", "example4", "quadratic", "exp_cos", "make",
+    "Problem", "grid", "example4", "quadratic", "exp_cos", "make", "make_device",
     "figure1_error", "initial_guess", "batch_specs", "arrival_trace",
     "SERVE_SIZES", "SERVE_WEIGHTS", "BATCH_SIZES",
 ]
@@ -80,12 +80,17 @@ def _random_spd(rng: np.random.Generator) -> np.ndarray:
     return (q * lam[None, :]) @ q.T
 
 
-def quadratic(n: int, seed: int = 0) -> Problem:
-    """u = x^T A x / 2 + b^T x with seeded SPD A (eigenvalues in [0.5, 2])."""
+def _quadratic_params(seed: int):
     rng = np.random.default_rng(seed)
     a = _random_spd(rng)
     a = 0.5 * (a + a.T)
     b = rng.uniform(-1.0, 1.0, size=3)
+    return a, b
+
+
+def quadratic(n: int, seed: int = 0) -> Problem:
+    """u = x^T A x / 2 + b^T x with seeded SPD A (eigenvalues in [0.5, 2])."""
+    a, b = _quadratic_params(seed)
     x, y, z = grid(n)
     u = (0.5 * (a[0, 0] * x * x + a[1, 1] * y * y + a[2, 2] * z * z)
          + a[0, 1] * x * y + a[0, 2] * x * z + a[1, 2] * y * z
@@ -193,3 +198,54 @@ def arrival_trace(count: int, rate: float, seed: int = 5000):
     kinds = np.where(rng.random(count) < 0.5, "quadratic", "exp_cos")
     return [(float(t[i]), str(kinds[i]), int(sizes[i]), seed + 1 + i)
             for i in range(count)]
+
+
+def make_device(kind: str, n: int, seed: int = 0, device="cuda", exact: bool = False):
+    """The problem of ``make(kind, n, seed)`` evaluated with torch on
+    ``device`` (float64): returns (u0, f) -- u0 holds g on the Dirichlet
+    layer and 0 inside -- plus u_exact when ``exact``.  Same seeded
+    parameters and formulas as the numpy generators; values can differ from
+    them in the last bits (device exp / cos).  For large served requests,
+    where building the data on the host would dominate."""
+    import torch
+
+    t = torch.arange(n + 1, dtype=torch.float64, device=device) / n
+    z, y, x = torch.meshgrid(t, t, t, indexing="ij")
+    r2 = x * x + y * y + z * z
+    if kind == "example4":
+        u = torch.exp(0.5 * r2)
+        f = (1.0 + r2) * torch.exp(1.5 * r2)
+    elif kind == "quadratic":
+        a, b = _quadratic_params(seed)
+        u = (0.5 * (a[0, 0] * x * x + a[1, 1] * y * y + a[2, 2] * z * z)
+             + a[0, 1] * x * y + a[0, 2] * x * z + a[1, 2] * y * z
+             + b[0] * x + b[1] * y + b[2] * z)
+        f = torch.full_like(u, float(np.linalg.det(a)))
+    elif kind == "exp_cos":
+        ks, phi, c = _cos_terms(np.random.default_rng(seed))
+        X = (x, y, z)
+        e = torch.exp(0.5 * r2)
+        u = e.clone()
+        H = [[e * ((1.0 if p == q else 0.0) + X[p] * X[q]) for q in range(3)] for p in range(3)]
+        for m in range(len(c)):
+            arg = math.pi * (ks[m, 0] * x + ks[m, 1] * y + ks[m, 2] * z) + phi[m]
+            ca = torch.cos(arg)
+            cm = 0.1 * c[m]
+            u += cm * ca
+            w = (-cm * math.pi ** 2) * ca
+            for p in range(3):
+                for q in range(3):
+                    if ks[m, p] * ks[m, q] != 0.0:
+                        H[p][q] = H[p][q] + w * (ks[m, p] * ks[m, q])
+        f = (H[0][0] * H[1][1] * H[2][2] + 2.0 * H[0][1] * H[1][2] * H[0][2]
+             - H[0][0] * H[1][2] ** 2 - H[1][1] * H[0][2] ** 2
+             - H[2][2] * H[0][1] ** 2)
+        del H, e
+    else:
+        raise ValueError(f"unknown problem kind {kind!r}")
+    del x, y, z, r2
+    u0 = u.clone()
+    u0[1:-1, 1:-1, 1:-1] = 0.0
+    if exact:
+        return u0, f, u
+    return u0, f

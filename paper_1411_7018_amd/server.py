@@ -1,0 +1,257 @@
+"""Continuous-batching server for Monge-Ampere solve requests.
+
+Requests arrive over time (e.g. ``problems.arrival_trace``: Poisson
+arrivals, grid sizes 65^3 .. 385^3).  The server keeps ONE resident batch
+(``ma_batch``): every tick advances each admitted solve by one step (a
+linear V-cycle of its Poisson initial guess, then FAS V-cycles, batched by
+level on the device).  Between ticks it
+
+  * retires the solves that finished (converged or failed), and
+  * admits queued requests while a slot is free and the HBM footprint of the
+    new solve -- its multigrid hierarchy plus its u and f arrays -- fits the
+    budget next to everything already resident.
+
+Hierarchies are kept after their request leaves (a per-size pool of idle
+solvers), so a later request of the same size allocates nothing; idle
+solvers are evicted, least recently used first, when a new request would
+not fit otherwise.  Admission is first-come first-served; with
+``skip_ahead`` a request that does not fit yet lets smaller ones behind it
+start.  A request larger than the whole budget is rejected (status
+MA_ERR_OOM) and the rest are still served.
+
+Each solve's arithmetic and stopping decisions are its own (the engine
+batches launches, never data), so a result is bitwise the same alone and in
+any mix.  The scheduling logic talks to a small backend interface, so it
+runs unchanged on the GPU (``GpuBackend``) and under a simulated clock in
+CPU tests.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+MA_ERR_OOM = 2
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    t_arrival: float          # seconds after the start of the run
+    kind: str
+    n: int
+    seed: int
+    t_admit: float | None = None
+    t_done: float | None = None
+    status: int | None = None   # 0 converged, else an ma_status
+    report: dict | None = None
+    u: object = None            # the solution (kept when keep_results)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class GpuBackend:
+    """Solvers, request data and the resident batch on the current GPU."""
+
+    def __init__(self, precision: str = "fp64", tol: float = 1e-8, max_slots: int = 64,
+                 **params):
+        from .solver import footprint_bytes
+
+        self.precision = precision
+        self.tol = tol
+        self.params = params
+        self.max_slots = max_slots
+        self._fp = footprint_bytes
+        self._hier = {}
+
+    def hierarchy_bytes(self, n: int) -> int:
+        if n not in self._hier:
+            self._hier[n] = int(self._fp(n, precision=self.precision, **self.params))
+        return self._hier[n]
+
+    def array_bytes(self, n: int) -> int:
+        return 2 * (n + 1) ** 3 * 8            # u and f, FP64
+
+    def new_solver(self, n: int):
+        from .solver import Solver
+
+        return Solver(n, precision=self.precision, **self.params)
+
+    def data(self, req: Request):
+        from .problems import make_device
+
+        return make_device(req.kind, req.n, req.seed)
+
+    def new_batch(self):
+        from .batch import ResidentBatch
+
+        return ResidentBatch(self.max_slots)
+
+    def add(self, batch, solver, u, f) -> int:
+        return batch.add(solver, u, f, tol=self.tol)
+
+    @staticmethod
+    def budget_default(reserve: float = 0.1) -> int:
+        import torch
+
+        free, _ = torch.cuda.mem_get_info()
+        return int(free * (1.0 - reserve))
+
+
+@dataclasses.dataclass
+class Stats:
+    completed: int
+    rejected: int
+    makespan: float
+    p50: float
+    p99: float
+    mean: float
+    solves_per_s: float
+    max_live: int
+    mean_live: float
+    peak_bytes: int
+    ticks: int
+    queued: int                 # requests admitted more than 1 ms after arrival
+
+    def as_dict(self) -> dict:
+        return dataclasses.asdict(self)
+
+
+class Server:
+    def __init__(self, backend, budget_bytes: int, max_slots: int = 64, pool: bool = True,
+                 skip_ahead: bool = False, keep_results: bool = False):
+        if not 1 <= max_slots <= 64:
+            raise ValueError("max_slots must be in 1..64")
+        self.be = backend
+        self.budget = int(budget_bytes)
+        self.max_slots = max_slots
+        self.pool = pool
+        self.skip_ahead = skip_ahead
+        self.keep_results = keep_results
+        self.used = 0                    # resident hierarchies + live arrays
+        self.peak = 0
+        self.idle = collections.OrderedDict()   # (n, serial) -> solver, LRU first
+        self._serial = 0
+        self.created = 0                 # solvers allocated
+        self.batch = None
+
+    # -- memory -----------------------------------------------------------
+    def _evict_one(self, protect) -> bool:
+        """Free the least recently used idle hierarchy other than protect."""
+        for k in self.idle:
+            if k != protect:
+                self.idle.pop(k)
+                self.used -= self.be.hierarchy_bytes(k[0])
+                return True
+        return False
+
+    def _try_admit(self, req: Request) -> str:
+        """'ok', 'wait' or 'reject'."""
+        n = req.n
+        arrays = self.be.array_bytes(n)
+        hier = self.be.hierarchy_bytes(n)
+        if arrays + hier > self.budget:
+            return "reject"
+        reuse = next((k for k in self.idle if k[0] == n), None)
+        need = arrays + (0 if reuse else hier)
+        while self.used + need > self.budget and self._evict_one(reuse):
+            pass
+        if self.used + need > self.budget:
+            return "wait"
+        if reuse:
+            solver = self.idle.pop(reuse)
+        else:
+            solver = self.be.new_solver(n)
+            self.created += 1
+        self.used += need
+        self.peak = max(self.peak, self.used)
+        u, f = self.be.data(req)
+        slot = self.be.add(self.batch, solver, u, f)
+        self._live[slot] = (req, solver, u, f)
+        return "ok"
+
+    # -- main loop --------------------------------------------------------
+    def run(self, requests, clock=time.perf_counter, sleep=time.sleep) -> Stats:
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        pending = collections.deque(reqs)
+        queue = collections.deque()
+        self._live = {}
+        self.batch = self.be.new_batch()
+        ticks, live_sum, max_live, queued = 0, 0, 0, 0
+        rejected = 0
+        t0 = clock()
+        try:
+            while pending or queue or self._live:
+                now = clock() - t0
+                while pending and pending[0].t_arrival <= now:
+                    queue.append(pending.popleft())
+                # admission, first come first served
+                blocked = []
+                while queue and len(self._live) < self.max_slots:
+                    req = queue[0]
+                    verdict = self._try_admit(req)
+                    if verdict == "wait":
+                        if not self.skip_ahead:
+                            break
+                        blocked.append(queue.popleft())
+                        continue
+                    queue.popleft()
+                    if verdict == "reject":
+                        req.status, req.t_admit, req.t_done = MA_ERR_OOM, now, now
+                        rejected += 1
+                        continue
+                    req.t_admit = now
+                    if req.t_admit > req.t_arrival + 1e-3:
+                        queued += 1
+                queue.extendleft(reversed(blocked))
+                if self._live:
+                    done = self.batch.tick()
+                    ticks += 1
+                    live_sum += len(self._live)
+                    max_live = max(max_live, len(self._live))
+                    tnow = clock() - t0
+                    for slot, code in done.items():
+                        req, solver, u, f = self._live.pop(slot)
+                        req.report = self.batch.report(slot)
+                        req.status = 0 if code == 1 else int(code)
+                        req.t_done = tnow
+                        if self.keep_results:
+                            req.u = u
+                        self.batch.remove(slot)
+                        self.used -= self.be.array_bytes(req.n)
+                        if self.pool:
+                            self._serial += 1
+                            self.idle[(req.n, self._serial)] = solver
+                        else:
+                            self.used -= self.be.hierarchy_bytes(req.n)
+                elif pending:
+                    sleep(max(0.0, pending[0].t_arrival - (clock() - t0)))
+                elif queue:
+                    # nothing live and the head cannot be admitted: only
+                    # idle hierarchies can be in the way, and eviction has
+                    # already been tried, so the request can never fit
+                    req = queue.popleft()
+                    req.status, req.t_admit, req.t_done = MA_ERR_OOM, now, now
+                    rejected += 1
+        finally:
+            self.batch.close()
+            self.batch = None
+        done = [r for r in reqs if r.status == 0]
+        lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+        t_first = reqs[0].t_arrival if reqs else 0.0
+        t_last = max((r.t_done for r in done), default=t_first)
+        makespan = max(t_last - t_first, 1e-12)
+        return Stats(completed=len(done), rejected=rejected, makespan=makespan,
+                     p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                     mean=float(lat.mean()), solves_per_s=len(done) / makespan,
+                     max_live=max_live, mean_live=live_sum / max(ticks, 1),
+                     peak_bytes=self.peak, ticks=ticks, queued=queued)
+
+
+def requests_from_trace(trace) -> list:
+    """``problems.arrival_trace`` tuples -> Request objects."""
+    return [Request(i, t, kind, n, seed) for i, (t, kind, n, seed) in enumerate(trace)]
