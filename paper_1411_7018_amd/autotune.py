@@ -54,9 +54,7 @@ def _time_ticks(solvers, us, fs, ticks: int) -> float:
     try:
         work = [u.clone() for u in us]
         for s, u, f in zip(solvers, work, fs):
-            # start where a solve's FAS cycles start (after the Poisson
-            # guess); an unreachable tolerance keeps every solve cycling
-            s.poisson_init(u, f)
+            # an unreachable tolerance keeps every solve cycling
             b.add(s, u, f, tol=1e-300, init_poisson=False)
         b.tick()                       # entry residuals, first tick, capture
         torch.cuda.synchronize()
@@ -78,12 +76,18 @@ def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE,
         raise ValueError("nothing to tune")
     if any(s.params.max_cycles < ticks + 1 for s in solvers):
         raise ValueError("max_cycles must exceed the number of timed ticks")
+    # time from where a solve's FAS cycles start: after the Poisson guess
+    starts = []
+    for s, u, f in zip(solvers, us, fs):
+        w = u.clone()
+        s.poisson_init(w, f)
+        starts.append(w)
     table = []
     for cn in coarse:
         for mb in blocks:
             for s in solvers:
                 s.retune(coarse_n=cn, max_blocks=mb)
-            t = min(_time_ticks(solvers, us, fs, ticks) for _ in range(2))
+            t = min(_time_ticks(solvers, starts, fs, ticks) for _ in range(2))
             table.append((cn, mb, t))
             if verbose:
                 print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d}: {1e3 * t:.3f} ms/tick",
