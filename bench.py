@@ -33,6 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Counter-measured bytes per launch of the dominant kernel (FETCH_SIZE and
+# WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
+# known size): profiles/k_batched_sweep_quadratic129_counters.md.  Valid for
+# the k_batched sweep kernel as profiled; reset to None when it changes.
+TRAFFIC = {("quadratic129", "fp64"): 36519302}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol)
@@ -54,21 +59,30 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, except batch64 (mixed)")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tuned", default=None,
+                    help="coarse_n,max_blocks to use instead of running the autotuner")
+    ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
+                    help="only run 20 plain device copies of MB megabytes (counter "
+                         "calibration for the traffic figures) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=None, help="served: HBM budget")
     return ap.parse_args()
 
 
-def roofline(reps):
+def roofline(reps, traffic=None):
     sec = sum(r["smooth_seconds"] for r in reps)
     by = sum(r["smooth_bytes"] for r in reps)
     la = sum(r["smooth_launches"] for r in reps)
     ach = by / sec / 1e9 if sec > 0 else 0.0
-    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_batched sweep, finest level (24 B per interior node per sweep)",
-            "avg_launch_us": 1e6 * sec / max(la, 1), "launches": la}
+    out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+           "kernel": "k_batched sweep, finest level (24 B per interior node per sweep)",
+           "avg_launch_us": 1e6 * sec / max(la, 1), "launches": la,
+           "alg_bytes_per_launch": by / max(la, 1)}
+    if traffic is not None:
+        out["traffic_unit"] = "bytes per launch (counters)"
+    return out
 
 
 def cpu_baseline(kind, n, seed, tol):
@@ -109,6 +123,34 @@ def base_line(args, value, steps, warmup, elapsed, lat, precision):
     }
 
 
+def pick_tuning(args, solvers, us, fs, ticks):
+    from paper_1411_7018_amd import autotune
+
+    if args.tuned:
+        cn, mb = (int(v) for v in args.tuned.split(","))
+        for s in solvers:
+            s.retune(coarse_n=cn, max_blocks=mb)
+        return autotune.Choice(cn, mb, float("nan"), [])
+    if args.no_tune:
+        return None
+    return autotune.tune(solvers, us, fs, ticks=ticks)
+
+
+def copy_calibration(mb):
+    """Plain device-to-device copies of a known size: the reference against
+    which the FETCH_SIZE / WRITE_SIZE counters of the solver kernels are
+    scaled."""
+    import torch
+
+    count = int(mb * 1e6) // 8
+    a = torch.ones(count, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": count * 8, "copies": 20}), flush=True)
+
+
 def tune_note(choice):
     if choice is None:
         return None
@@ -119,7 +161,7 @@ def tune_note(choice):
 def run_single(args, precision):
     import torch
 
-    from paper_1411_7018_amd import Solver, autotune, problems as P
+    from paper_1411_7018_amd import Solver, problems as P
 
     kind, n, seed, tol = SINGLE[args.workload]
     steps = args.steps or 20
@@ -130,9 +172,7 @@ def run_single(args, precision):
     f = torch.from_numpy(prob.f).to(dev)
     u = torch.empty_like(u_init)
     s = Solver(n, precision=precision, profile=1)
-    choice = None
-    if not args.no_tune:
-        choice = autotune.tune([s], [u_init], [f])
+    choice = pick_tuning(args, [s], [u_init], [f], ticks=4)
 
     def step():
         u.copy_(u_init)
@@ -159,7 +199,7 @@ def run_single(args, precision):
     out.update({"updates_per_s": sum(r["point_updates"] for r in reps) / elapsed,
                 "cycles": last["cycles"], "init_cycles": last["init_cycles"],
                 "rel_res": last["rel_res"], "max_err_vs_exact": err,
-                "roofline": roofline(reps)})
+                "roofline": roofline(reps, TRAFFIC.get((args.workload, precision)))})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(kind, n, seed, tol)
     return out
@@ -168,7 +208,7 @@ def run_single(args, precision):
 def run_batch(args, precision):
     import torch
 
-    from paper_1411_7018_amd import Solver, autotune, problems as P
+    from paper_1411_7018_amd import Solver, problems as P
     from paper_1411_7018_amd.batch import solve_batch
 
     steps = args.steps or 5
@@ -179,9 +219,7 @@ def run_batch(args, precision):
     fs = [d[1] for d in data]
     us = [torch.empty_like(u) for u in us0]
     solvers = [Solver(n, precision=precision, profile=1) for _, n, _ in specs]
-    choice = None
-    if not args.no_tune:
-        choice = autotune.tune(solvers, us0, fs, ticks=3)
+    choice = pick_tuning(args, solvers, us0, fs, ticks=3)
 
     def step():
         for u, u0 in zip(us, us0):
@@ -276,6 +314,9 @@ def main():
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (the "
                                    "multi-GPU layout is documented as a design only)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     precision = args.precision or ("mixed" if args.workload == "batch64" else "fp64")
     if args.workload in SINGLE:
         out = run_single(args, precision)
