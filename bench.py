@@ -60,7 +60,8 @@ def parse():
                     help="default: fp64, except batch64 (mixed)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuned", default=None,
-                    help="coarse_n,max_blocks to use instead of running the autotuner")
+                    help="coarse_n,max_blocks[,strip_rows] to use instead of running the "
+                         "autotuner")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (counter "
                          "calibration for the traffic figures) and exit")
@@ -127,10 +128,11 @@ def pick_tuning(args, solvers, us, fs, ticks):
     from paper_1411_7018_amd import autotune
 
     if args.tuned:
-        cn, mb = (int(v) for v in args.tuned.split(","))
+        vals = [int(v) for v in args.tuned.split(",")]
+        cn, mb, sr = (vals + [0])[:3]
         for s in solvers:
-            s.retune(coarse_n=cn, max_blocks=mb)
-        return autotune.Choice(cn, mb, float("nan"), [])
+            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
+        return autotune.Choice(cn, mb, sr, float("nan"), [])
     if args.no_tune:
         return None
     return autotune.tune(solvers, us, fs, ticks=ticks)
@@ -155,7 +157,7 @@ def tune_note(choice):
     if choice is None:
         return None
     return {"coarse_n": choice.coarse_n, "max_blocks": choice.max_blocks,
-            "ms_per_tick": 1e3 * choice.seconds_per_tick}
+            "strip_rows": choice.strip_rows, "ms_per_tick": 1e3 * choice.seconds_per_tick}
 
 
 def run_single(args, precision):

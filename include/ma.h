@@ -88,6 +88,8 @@ typedef struct {
                               single-workgroup kernel per solve; 0: off         */
     int max_blocks;        /* cap on the blocks of one batched launch (multiple
                               of 8, 0 automatic = 16384)                         */
+    int strip_rows;        /* x-rows per y-strip in the work order of a batched
+                              launch (strips are walked along z; 0 automatic)    */
 } ma_params;
 
 typedef struct {
@@ -143,10 +145,10 @@ const char *ma_last_error(const ma_solver *s);
 ma_status ma_set_stream(ma_solver *s, void *hip_stream);
 
 /* Change the launch shape of later cycles without touching the hierarchy:
- * coarse_n and max_blocks as in ma_params (the autotuner's knobs).  The
- * arithmetic, and so every result, is the same for every value.
+ * coarse_n, max_blocks and strip_rows as in ma_params (the autotuner's
+ * knobs).  The arithmetic, and so every result, is the same for every value.
  * Errors: MA_ERR_ARG for values outside their ranges (nothing changes). */
-ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks);
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows);
 
 /* Solve det(D^2 u) = f (Algorithm 1 repeated under the stopping rule of
  * Section 4): run V(nu1,nu2) cycles until the discrete L2 residual is

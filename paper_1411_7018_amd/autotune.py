@@ -8,8 +8,10 @@ cut into launches:
     latency hiding on mid-size grids).
   * ``coarse_n``   -- levels with n <= coarse_n run inside the
     single-workgroup coarse-level kernel instead of one launch per phase.
+  * ``strip_rows`` -- the width of the y-strips in which a launch walks its
+    rows along z: narrow strips keep the planes a stencil re-reads in L2.
 
-``tune`` times every candidate pair on the device, on the caller's own
+``tune`` times the candidates on the device, on the caller's own
 solvers and data (a copy of u), with one tick per candidate for graph
 capture followed by timed ticks, and leaves the solvers retuned to the
 fastest pair.  All candidates give bitwise the same results, so tuning never
@@ -25,20 +27,22 @@ import time
 
 import torch
 
-BLOCKS = (2048, 4096, 8192, 16384, 32768)
+BLOCKS = (4096, 8192, 16384, 32768, 65536)
 COARSE = (0, 8, 16, 32)
+STRIPS = (8, 32, 128, 4096)
 
 
 @dataclasses.dataclass
 class Choice:
     coarse_n: int
     max_blocks: int
+    strip_rows: int
     seconds_per_tick: float
-    table: list          # [(coarse_n, max_blocks, seconds_per_tick), ...]
+    table: list          # [(coarse_n, max_blocks, strip_rows, seconds_per_tick), ...]
 
     def as_dict(self) -> dict:
         return {"coarse_n": self.coarse_n, "max_blocks": self.max_blocks,
-                "seconds_per_tick": self.seconds_per_tick,
+                "strip_rows": self.strip_rows, "seconds_per_tick": self.seconds_per_tick,
                 "table": [list(r) for r in self.table]}
 
 
@@ -67,11 +71,15 @@ def _time_ticks(solvers, us, fs, ticks: int) -> float:
         b.close()
 
 
-def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE,
+def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE, strips=STRIPS,
          verbose: bool = False) -> Choice:
-    """Time each (coarse_n, max_blocks) pair on one batched tick of these
-    solves and retune the solvers to the fastest.  The solves must fit one
-    batch (at most 64, shared smoothing parameters)."""
+    """Pick the launch shape of one batched tick of these solves and retune
+    the solvers to it.  The knobs barely interact (coarse_n moves work
+    between the coarse-level kernel and the row kernels; max_blocks and
+    strip_rows shape the row kernels), so they are searched one after the
+    other -- coarse_n x max_blocks on the default strips, then strip_rows --
+    instead of over the full product.  The solves must fit one batch (at
+    most 64, shared smoothing parameters)."""
     if not solvers:
         raise ValueError("nothing to tune")
     if any(s.params.max_cycles < ticks + 1 for s in solvers):
@@ -83,19 +91,27 @@ def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE,
         s.poisson_init(w, f)
         starts.append(w)
     table = []
+
+    def trial(cn, mb, sr):
+        for s in solvers:
+            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
+        t = min(_time_ticks(solvers, starts, fs, ticks) for _ in range(2))
+        table.append((cn, mb, sr, t))
+        if verbose:
+            print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d} strip_rows={sr:4d}: "
+                  f"{1e3 * t:.3f} ms/tick", flush=True)
+        return t
+
     for cn in coarse:
         for mb in blocks:
-            for s in solvers:
-                s.retune(coarse_n=cn, max_blocks=mb)
-            t = min(_time_ticks(solvers, starts, fs, ticks) for _ in range(2))
-            table.append((cn, mb, t))
-            if verbose:
-                print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d}: {1e3 * t:.3f} ms/tick",
-                      flush=True)
-    cn, mb, t = min(table, key=lambda r: r[2])
+            trial(cn, mb, 0)
+    cn, mb, _, _ = min(table, key=lambda r: r[3])
+    for sr in strips:
+        trial(cn, mb, sr)
+    cn, mb, sr, t = min(table, key=lambda r: r[3])
     for s in solvers:
-        s.retune(coarse_n=cn, max_blocks=mb)
-    return Choice(cn, mb, t, table)
+        s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
+    return Choice(cn, mb, sr, t, table)
 
 
 def load(path: str, k: str) -> dict | None:

@@ -21,19 +21,30 @@ constexpr int kDefaultMaxBlocks = 16384;
 constexpr int kTailThreads = 512;      // threads of the coarse-level kernel
 constexpr int kMaxTail = 6;            // levels per solve inside that kernel
 
-// One grid of one solve inside a batched launch.  The grid's work items are
-// [start, start + gx*gy*gz), item = bx + gx*(by + gy*bz); every item is one
-// wavefront handling 64 nodes of one x-row.
+// One grid of one solve inside a batched launch.  Every work item is one
+// wavefront handling 64 nodes of one x-row (bx, by, bz) of a gx x gy x gz
+// decomposition.  The items of a grid are ordered in y-strips of w rows
+// walked along z: item - start = bx + gx*(jj + w*(bz + gz*strip)), by =
+// strip*w + jj (items with by >= gy are idle), so the rows a stencil
+// reads above, below and on both sides are fetched while they are still
+// in the XCD's L2.
 struct GridItem {
     int n;         // intervals per side of this grid
     int start;     // first work item
-    int gx, gy;    // item decomposition (gz implied by the next start)
+    int gx, gy, gz;
+    int w;         // rows per y-strip
     int slot;      // solve index: norm and counter slot
-    int pbase;     // first partial-sum slot (norm lists)
+    int pbase;     // first partial-sum slot (norm lists): gx*gy*gz slots
     double s;      // 1/h^2 of this grid
     double hk;     // h^2/2 (nonlinear update) or 1/(6s) (linear update)
     void *p[6];    // operands, meaning set by the list kind
 };
+
+// Work items of a grid, idle padding of the last y-strip included.
+inline int padded_items(int gx, int gy, int gz, int w)
+{
+    return gx * ((gy + w - 1) / w) * w * gz;
+}
 
 // Lists live in one device buffer at a fixed stride of list_bytes(slots):
 // the header followed by ngrids descriptors (g[] below is only the bound).
@@ -108,7 +119,7 @@ class Engine {
 
     // Define the solves (at most kMaxGrids) and the stream the caller orders
     // its work on.  All solvers must share nu1, nu2, nu0, order, restriction,
-    // precision, inner_cycles, coarse_n and max_blocks.  graphs: replay
+    // precision, inner_cycles, coarse_n, max_blocks and strip_rows.  graphs: replay
     // ticks from captured hipGraphs.
     ma_status set(const std::vector<SolveRef> &solves, hipStream_t user, bool graphs,
                   bool profile);
@@ -160,7 +171,8 @@ class Engine {
     int D_ = 0;      // multi-block depth of the active solves
     int Dall_ = 0;   // full depth of the active solves
     int nu1_ = 2, nu2_ = 2, nu0_ = 1, order_ = 0, rmode_ = 0, inner_ = 2;
-    int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks;
+    int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks, strip_rows_ = 0;
+    int strip_width(int gy) const;
 
     std::vector<char> hbuf_;               // host copy of the lists and the tail table
     std::vector<size_t> loff_;             // byte offset of each list

@@ -324,10 +324,14 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
         const GridItem &G = L->g[g];
         const int local = it - G.start;
         const int bx = local % G.gx;
-        const int rest = local / G.gx;
-        const int by = rest % G.gy;
-        const int bz = rest / G.gy;
-        run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, int(threadIdx.x), ncount, nfall);
+        int rest = local / G.gx;
+        const int jj = rest % G.w;
+        rest /= G.w;
+        const int bz = rest % G.gz;
+        const int by = (rest / G.gz) * G.w + jj;
+        if (by < G.gy)
+            run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, int(threadIdx.x), ncount,
+                                             nfall);
     }
 }
 
@@ -343,8 +347,7 @@ __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__rest
     if (g >= L->ngrids)
         return;
     const GridItem &G = L->g[g];
-    const int end = (g + 1 < L->ngrids) ? L->g[g + 1].start : L->total;
-    const int cnt = end - G.start;
+    const int cnt = G.gx * G.gy * G.gz;
     double v = 0.0;
     for (int q = threadIdx.x; q < cnt; q += 1024)
         v += partials[G.pbase + q];
@@ -697,10 +700,11 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         else if (p.nu1 != p0->nu1 || p.nu2 != p0->nu2 || p.nu0 != p0->nu0 || p.order != p0->order ||
                  p.restriction != p0->restriction || p.precision != p0->precision ||
                  p.inner_cycles != p0->inner_cycles || p.coarse_n != p0->coarse_n ||
-                 p.max_blocks != p0->max_blocks)
+                 p.max_blocks != p0->max_blocks || p.strip_rows != p0->strip_rows)
             return fail(MA_ERR_ARG,
                         "solvers in one batch must share smoothing counts, ordering, "
-                        "restriction, precision, inner cycles, coarse_n and max_blocks");
+                        "restriction, precision, inner cycles, coarse_n, max_blocks and "
+                        "strip_rows");
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
@@ -729,6 +733,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     mixed_ = p0->precision == MA_MIXED;
     coarse_n_ = p0->coarse_n;
     max_blocks_ = p0->max_blocks > 0 ? p0->max_blocks : kDefaultMaxBlocks;
+    strip_rows_ = p0->strip_rows;
     fused_ = fused;
     built_ = false;
     if (!stream_) {
@@ -785,6 +790,14 @@ ma_status Engine::read_counters(std::vector<unsigned long long> &nonconvex,
 }
 
 int Engine::levels(int i) const { return int(solves_[i].s->lv.size()); }
+
+// Rows per y-strip: strip_rows when set, else 32 (a strip of 32 rows walked
+// along z keeps ~20 planes of it in flight per XCD within the 4 MB L2).
+int Engine::strip_width(int gy) const
+{
+    const int w = strip_rows_ > 0 ? strip_rows_ : 32;
+    return std::max(1, std::min(w, gy));
+}
 
 int Engine::multiblock_levels(int i) const
 {
@@ -934,7 +947,9 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             int gx, gy, gz;
             const int n = mixed ? solves_[i].s->mx[d].n : solves_[i].s->lv[d].n;
             item_dims(kind, order_, n, &gx, &gy, &gz);
-            bound += long(gx) * gy * gz;
+            const int w = strip_width(gy);
+            const int items = padded_items(gx, gy, gz, w);
+            bound += items;
             if (!active[i])
                 continue;
             if (L.ngrids == kMaxGrids) {
@@ -944,12 +959,14 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             GridItem G = grid(kind, i, d, mode);
             G.gx = gx;
             G.gy = gy;
+            G.gz = gz;
+            G.w = w;
             G.start = start;
             if (partial) {
                 G.pbase = pnext;
                 pnext += gx * gy * gz;
             }
-            start += gx * gy * gz;
+            start += items;
             L.g[L.ngrids++] = G;
         }
         L.total = start;
@@ -1204,6 +1221,7 @@ std::vector<int> Engine::shape() const
     s.push_back(int(stride_));
     s.push_back(int(toff_));
     s.push_back(tail_blocks_);
+    s.push_back(strip_rows_);
     s.push_back(int(loff_.size()));
     s.insert(s.end(), lgrid_.begin(), lgrid_.end());
     return s;

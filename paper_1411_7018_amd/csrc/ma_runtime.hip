@@ -67,6 +67,10 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "max_blocks must be 0 or a multiple of 8 up to 2^20";
         return false;
     }
+    if (p->strip_rows < 0 || p->strip_rows > 4096) {
+        why = "strip_rows must be in 0..4096";
+        return false;
+    }
     if (p->graphs != 0 && p->graphs != 1) {
         why = "graphs must be 0 or 1";
         return false;
@@ -194,13 +198,14 @@ ma_status ma_set_stream(ma_solver *s, void *hip_stream)
     return MA_OK;
 }
 
-ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks)
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows)
 {
     if (!s)
         return MA_ERR_ARG;
     ma_params q = s->p;
     q.coarse_n = coarse_n;
     q.max_blocks = max_blocks;
+    q.strip_rows = strip_rows;
     std::string why;
     if (!valid_params(&q, why))
         return s->fail(MA_ERR_ARG, why);

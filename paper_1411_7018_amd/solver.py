@@ -73,12 +73,14 @@ class Solver:
     def set_stream(self, stream) -> None:
         L.ma_set_stream(self.handle, _stream_handle(stream))
 
-    def retune(self, coarse_n: int | None = None, max_blocks: int | None = None) -> None:
+    def retune(self, coarse_n: int | None = None, max_blocks: int | None = None,
+               strip_rows: int | None = None) -> None:
         """Change the launch shape of later cycles (results are unchanged)."""
         cn = self.params.coarse_n if coarse_n is None else int(coarse_n)
         mb = self.params.max_blocks if max_blocks is None else int(max_blocks)
-        L.ma_retune(self.handle, cn, mb)
-        self.params.coarse_n, self.params.max_blocks = cn, mb
+        sr = self.params.strip_rows if strip_rows is None else int(strip_rows)
+        L.ma_retune(self.handle, cn, mb, sr)
+        self.params.coarse_n, self.params.max_blocks, self.params.strip_rows = cn, mb, sr
 
     def _grid(self, t: torch.Tensor, n: int | None = None, name: str = "u") -> int:
         n = self.n if n is None else n
