@@ -87,6 +87,12 @@ def lib():
         L.mao_poisson_init.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(Params)]
         L.mao_solve.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(Params),
                                 ctypes.POINTER(Report), _DP, ctypes.c_int]
+        L.mao_inject.argtypes = [ctypes.c_int, _DP, _DP]
+        L.mao_inject.restype = None
+        L.mao_fmg_interp.argtypes = [ctypes.c_int, _DP, _DP]
+        L.mao_fmg_interp.restype = None
+        L.mao_fmg.argtypes = [ctypes.c_int, _DP, _DP, ctypes.POINTER(Params)]
+        L.mao_fmg.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -116,10 +122,21 @@ def default_rmode(order) -> int:
     return RESTRICT_HALF if _order(order) == ORDER_LEX else RESTRICT_FULL
 
 
+INIT_NONE, INIT_POISSON, INIT_FMG = 0, 1, 2
+
+
 def params(nu1=2, nu2=2, nu0=1, order="4c", max_cycles=100, tol=1e-10, init=True,
            init_tol=1e-6, init_max_cycles=30, rmode=None) -> Params:
+    """init: True / "poisson" (Poisson guess), "fmg" (one FMG-FAS iteration,
+    Algorithm 2, counted as the first cycle) or False / "none"."""
     rm = default_rmode(order) if rmode is None else int(rmode)
-    return Params(nu1, nu2, nu0, _order(order), rm, max_cycles, tol, 1 if init else 0,
+    if init is True or init == "poisson":
+        iv = INIT_POISSON
+    elif init == "fmg":
+        iv = INIT_FMG
+    else:
+        iv = INIT_NONE
+    return Params(nu1, nu2, nu0, _order(order), rm, max_cycles, tol, iv,
                   init_tol, init_max_cycles)
 
 
@@ -196,6 +213,31 @@ def restrict(uf: np.ndarray, rf: np.ndarray, op: str = "ma", rmode: int = RESTRI
 
 def prolong_correct(uf: np.ndarray, uc: np.ndarray, wc: np.ndarray) -> None:
     lib().mao_prolong_correct(_n_of(uf), _ptr(uf), _ptr(uc), _ptr(wc))
+
+
+def inject(vf: np.ndarray) -> np.ndarray:
+    """Injection onto the grid with half the intervals (every coarse node)."""
+    nf = _n_of(vf)
+    vc = np.empty((nf // 2 + 1,) * 3)
+    lib().mao_inject(nf, _ptr(vf), _ptr(vc))
+    return vc
+
+
+def fmg_interp(uc: np.ndarray, uf: np.ndarray) -> None:
+    """FMG interpolation of the coarse uc into the interior of uf."""
+    nc = _n_of(uc)
+    if _n_of(uf) != 2 * nc:
+        raise ValueError("uf must have twice the intervals of uc")
+    lib().mao_fmg_interp(nc, _ptr(uc), _ptr(uf))
+
+
+def fmg(u: np.ndarray, f: np.ndarray, p: Params | None = None) -> int:
+    """One FMG-FAS iteration (Algorithm 2) in place; u's interior is ignored."""
+    p = p or params()
+    nc = lib().mao_fmg(_n_of(u), _ptr(u), _ptr(f), ctypes.byref(p))
+    if nc < 0:
+        raise MemoryError("oracle allocation failed")
+    return nc
 
 
 def poisson_rhs(f: np.ndarray) -> np.ndarray:

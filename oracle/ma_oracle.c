@@ -447,7 +447,8 @@ typedef struct {
     int rmode;               /* residual restriction: 0 half-, 1 full weighting */
     int max_cycles;
     double tol;              /* relative L2 residual; < 0 selects limit mode */
-    int init;                /* 1: Poisson initial guess, 0: use u as given */
+    int init;                /* 0: use u as given, 1: Poisson initial guess,
+                                2: one FMG-FAS iteration (Algorithm 2) */
     double init_tol;         /* relative linear residual for the Poisson guess */
     int init_max_cycles;
 } mao_params;
@@ -579,6 +580,126 @@ int mao_poisson_init(int n, double *u, const double *f, const mao_params *p)
     return cyc;
 }
 
+/* ------------------------------------------------------------------ */
+/* Full multigrid (Algorithm 2)                                         */
+/* ------------------------------------------------------------------ */
+
+/* Injection (the operator written with a tilde in Section 3): the coarse
+ * value at every coarse node, boundary included, is the fine value at the
+ * same point. */
+void mao_inject(int nf, const double *vf, double *vc)
+{
+    const int nc = nf / 2;
+    for (int K = 0; K <= nc; ++K)
+        for (int J = 0; J <= nc; ++J)
+            for (int I = 0; I <= nc; ++I)
+                vc[IX(nc, I, J, K)] = vf[IX(nf, 2 * I, 2 * J, 2 * K)];
+}
+
+/* 1D weights of the FMG interpolation at fine index i of a fine grid with
+ * nf = 2 nc intervals: a coarse node copies (weight 1); a midpoint takes the
+ * cubic Lagrange value through the four nearest coarse nodes, one-sided
+ * next to the boundary, and the quadratic value when the coarse grid has
+ * only three nodes.  Writes the first coarse index and up to 4 weights;
+ * returns their count. */
+static int fmg_weights(int nc, int i, int *first, double *w)
+{
+    if ((i & 1) == 0) {
+        *first = i / 2;
+        w[0] = 1.0;
+        return 1;
+    }
+    const int I0 = (i - 1) / 2;          /* midpoint between I0 and I0 + 1 */
+    if (nc < 3) {                         /* nodes 0, 1, 2: quadratic */
+        *first = 0;
+        if (I0 == 0) {
+            w[0] = 3.0 / 8.0; w[1] = 6.0 / 8.0; w[2] = -1.0 / 8.0;
+        } else {
+            w[0] = -1.0 / 8.0; w[1] = 6.0 / 8.0; w[2] = 3.0 / 8.0;
+        }
+        return 3;
+    }
+    if (I0 == 0) {                        /* nodes 0..3, point at 0.5 */
+        *first = 0;
+        w[0] = 5.0 / 16.0; w[1] = 15.0 / 16.0; w[2] = -5.0 / 16.0; w[3] = 1.0 / 16.0;
+    } else if (I0 + 1 == nc) {            /* nodes nc-3..nc, point at nc-0.5 */
+        *first = nc - 3;
+        w[0] = 1.0 / 16.0; w[1] = -5.0 / 16.0; w[2] = 15.0 / 16.0; w[3] = 5.0 / 16.0;
+    } else {                              /* nodes I0-1..I0+2 */
+        *first = I0 - 1;
+        w[0] = -1.0 / 16.0; w[1] = 9.0 / 16.0; w[2] = 9.0 / 16.0; w[3] = -1.0 / 16.0;
+    }
+    return 4;
+}
+
+/* FMG interpolation (Algorithm 2, step 4): the interior of the fine grid
+ * from the coarse grid by the tensor product of the 1D rule above; the
+ * fine boundary layer is left as it is (Dirichlet data). */
+void mao_fmg_interp(int nc, const double *uc, double *uf)
+{
+    const int nf = 2 * nc;
+    for (int k = 1; k < nf; ++k) {
+        int fk, ck;
+        double wk[4];
+        ck = fmg_weights(nc, k, &fk, wk);
+        for (int j = 1; j < nf; ++j) {
+            int fj, cj;
+            double wj[4];
+            cj = fmg_weights(nc, j, &fj, wj);
+            for (int i = 1; i < nf; ++i) {
+                int fi, ci;
+                double wi[4];
+                ci = fmg_weights(nc, i, &fi, wi);
+                double v = 0.0;
+                for (int c = 0; c < ck; ++c)
+                    for (int b = 0; b < cj; ++b)
+                        for (int a = 0; a < ci; ++a)
+                            v += wk[c] * wj[b] * wi[a] * uc[IX(nc, fi + a, fj + b, fk + c)];
+                uf[IX(nf, i, j, k)] = v;
+            }
+        }
+    }
+}
+
+/* Algorithm 2 at level l: w_l := FMG(l, b_l).  u holds the Dirichlet data
+ * of level l on its boundary layer on entry. */
+static long fmg_rec(hier *H, int l, double *u, const double *b, const mao_params *p)
+{
+    const int n = H->ns[l];
+    long nc = 0;
+    if (l == H->L - 1) {
+        /* coarsest: initial guess zero inside, nu0 sweeps */
+        for (int k = 1; k < n; ++k)
+            for (int j = 1; j < n; ++j)
+                for (int i = 1; i < n; ++i)
+                    u[IX(n, i, j, k)] = 0.0;
+        for (int s = 0; s < p->nu0; ++s)
+            nc += sweep_op(n, u, b, p->order, 0);
+        return nc;
+    }
+    mao_inject(n, b, H->b[l + 1]);       /* b_H := injection of b_h */
+    mao_inject(n, u, H->u[l + 1]);       /* boundary data of level l + 1 */
+    nc += fmg_rec(H, l + 1, H->u[l + 1], H->b[l + 1], p);
+    mao_fmg_interp(H->ns[l + 1], H->u[l + 1], u);
+    nc += vcycle_rec(H, l, u, b, p, 0);  /* one FAS V-cycle */
+    return nc;
+}
+
+/* One FMG-FAS iteration (Algorithm 2) on det(D^2 u) = f; u carries the
+ * Dirichlet data on its boundary layer, its interior is not read.  Returns
+ * -1 on allocation failure, otherwise the number of non-certified updates. */
+long mao_fmg(int n, double *u, const double *f, const mao_params *p)
+{
+    hier H;
+    if (hier_alloc(&H, n)) {
+        hier_free(&H);
+        return -1;
+    }
+    const long nc = fmg_rec(&H, 0, u, f, p);
+    hier_free(&H);
+    return nc;
+}
+
 /* Full solve (Algorithm 1 repeated under the Section 4 stopping rule).
  * hist (optional, hist_cap entries) receives the discrete L2 residual after
  * each cycle.  Limit mode (tol < 0): cycle until the residual has failed to
@@ -591,7 +712,7 @@ int mao_solve(int n, double *u, const double *f, const mao_params *p, mao_report
     struct timespec t0, t1;
     clock_gettime(CLOCK_MONOTONIC, &t0);
     memset(rep, 0, sizeof(*rep));
-    if (p->init) {
+    if (p->init == 1) {
         rep->init_cycles = mao_poisson_init(n, u, f, p);
         if (rep->init_cycles < 0)
             return -1;
@@ -601,15 +722,37 @@ int mao_solve(int n, double *u, const double *f, const mao_params *p, mao_report
         hier_free(&H);
         return -1;
     }
+    if (p->init == 2) {
+        /* Section 4 protocol: r^0 is the residual of the start that has
+         * the Dirichlet data and zero inside; one FMG-FAS iteration
+         * (Algorithm 2) counts as the first cycle */
+        for (int k = 1; k < n; ++k)
+            for (int j = 1; j < n; ++j)
+                for (int i = 1; i < n; ++i)
+                    u[IX(n, i, j, k)] = 0.0;
+    }
     rep->res0 = l2_from_sumsq(n, residual_op(n, u, f, NULL, 0));
     rep->res = rep->res0;
+    if (p->init == 2) {
+        rep->nonconvex += fmg_rec(&H, 0, u, f, p);
+        rep->init_cycles = 1;
+        rep->res = l2_from_sumsq(n, residual_op(n, u, f, NULL, 0));
+        if (hist && hist_cap > 0)
+            hist[0] = rep->res;
+    }
     double best = rep->res0;
     int stall = 0;
     int status = 1;
     if (rep->res0 == 0.0 && p->tol >= 0.0) {
         status = 0;
     } else {
-        for (int c = 0; c < p->max_cycles; ++c) {
+        const int c0 = p->init == 2 ? 1 : 0;   /* FMG is cycle 1 */
+        rep->cycles = c0;
+        if (c0 && p->tol >= 0.0 && rep->res <= p->tol * rep->res0) {
+            status = 0;
+            rep->cycles = 1;
+        }
+        for (int c = c0; status != 0 && c < p->max_cycles; ++c) {
             rep->nonconvex += vcycle_rec(&H, 0, u, f, p, 0);
             rep->cycles = c + 1;
             rep->res = l2_from_sumsq(n, residual_op(n, u, f, NULL, 0));
