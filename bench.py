@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--workload", default="quadratic129", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, except batch64 (mixed)")
+    ap.add_argument("--init", default="poisson", choices=["poisson", "fmg"],
+                    help="single solves: Poisson initial guess (default) or the Section 4 "
+                         "protocol (one FMG-FAS iteration as the first cycle)")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuned", default=None,
                     help="coarse_n,max_blocks[,strip_rows] to use instead of running the "
@@ -178,7 +181,7 @@ def run_single(args, precision):
 
     def step():
         u.copy_(u_init)
-        return s.solve(u, f, tol=tol)
+        return s.solve(u, f, tol=tol, init=args.init)
 
     for _ in range(warmup):
         step()
@@ -195,9 +198,12 @@ def run_single(args, precision):
     err = float(np.abs(u.cpu().numpy() - prob.u_exact).max())
     out = base_line(args, steps / elapsed, steps, warmup, elapsed, lat, precision)
     out["config"] = {
-        "workload": f"{kind} {n + 1}^3 single solve, seed {seed}, tol {tol:g}, Poisson "
-                    f"initial guess, FAS V(2,2), 4-colour nonlinear GS, {precision}",
-        "n": n, "tol": tol, "precision": precision, "tuned": tune_note(choice)}
+        "workload": f"{kind} {n + 1}^3 single solve, seed {seed}, tol {tol:g}, "
+                    + ("Poisson initial guess" if args.init == "poisson" else
+                       "FMG-FAS start (r0 of the zero-interior start)")
+                    + f", FAS V(2,2), 4-colour nonlinear GS, {precision}",
+        "n": n, "tol": tol, "precision": precision, "init": args.init,
+        "tuned": tune_note(choice)}
     out.update({"updates_per_s": sum(r["point_updates"] for r in reps) / elapsed,
                 "cycles": last["cycles"], "init_cycles": last["init_cycles"],
                 "rel_res": last["rel_res"], "max_err_vs_exact": err,

@@ -67,6 +67,12 @@ typedef enum {
  * linear V-cycles with the same ordering and transfers). */
 #define MA_INIT_POISSON 1u
 
+/* ma_solve flag: the protocol of Section 4 -- r^0 is the residual of the
+ * start that holds the Dirichlet data of u and zero inside, one FMG-FAS
+ * iteration (Algorithm 2, see ma_fmg) is the first cycle, FAS V-cycles
+ * follow until the tolerance.  Excludes MA_INIT_POISSON. */
+#define MA_INIT_FMG 2u
+
 typedef struct {
     int n;                 /* intervals per side, n >= 2; grid (n+1)^3, h = 1/n  */
     int nu1, nu2, nu0;     /* pre-, post-smoothing sweeps, sweeps on the coarsest
@@ -93,8 +99,11 @@ typedef struct {
 } ma_params;
 
 typedef struct {
-    int cycles;            /* FAS V-cycles run (MA_MIXED: FP32 inner cycles)     */
-    int outer;             /* MA_MIXED outer FP64 corrections (0 for MA_FP64)    */
+    int cycles;            /* FAS V-cycles run (MA_MIXED: FP32 inner cycles);
+                              with MA_INIT_FMG the FMG-FAS iteration counts as
+                              the first (Section 4's 'Iter')                    */
+    int outer;             /* MA_MIXED outer FP64 corrections, the FMG start
+                              included (0 for MA_FP64)                           */
     int init_cycles;       /* linear V-cycles of the Poisson initial guess       */
     int converged;         /* 1 when res <= tol * res0                           */
     double res0;           /* discrete L2 residual sqrt(h^3 sum r^2) of u0       */
@@ -191,6 +200,17 @@ ma_status ma_restrict(ma_solver *s, const double *u, const double *f, double *w_
  * fine interior nodes, trilinear interpolation (weights 1, 1/2, 1/4, 1/8).
  * u: device (n+1)^3 in place; u_c, w_c: device (n/2+1)^3. */
 ma_status ma_prolong_correct(ma_solver *s, double *u, const double *u_c, const double *w_c);
+
+/* One FMG-FAS iteration (Algorithm 2): f and the Dirichlet layer of u are
+ * injected down the hierarchy (b_H := injection of b_h); on the coarsest
+ * grid u starts from zero inside and takes nu0 sweeps; on the way up each
+ * level's u is the FMG interpolation of the coarser one (tensor product of
+ * 4-point cubic Lagrange rules, one-sided next to the boundary, quadratic
+ * on a 3-node coarse grid; the paper asks for a cubic interpolation without
+ * fixing the stencil) followed by one FAS V-cycle.  The interior of u on
+ * entry is not read.  FP64 for both precisions.  nonconvex_host (may be
+ * NULL) receives the non-certified updates.  Synchronises the stream. */
+ma_status ma_fmg(ma_solver *s, double *u, const double *f, long long *nonconvex_host);
 
 /* The MA_INIT_POISSON initial guess alone: linear V-cycles on
  * Lap_h u = 3 f^{1/3} until the relative linear residual is <= init_tol or

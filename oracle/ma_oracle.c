@@ -668,12 +668,16 @@ static long fmg_rec(hier *H, int l, double *u, const double *b, const mao_params
     const int n = H->ns[l];
     long nc = 0;
     if (l == H->L - 1) {
-        /* coarsest: initial guess zero inside, nu0 sweeps */
+        /* coarsest: initial guess zero inside, then an approximate solve.
+         * The paper's coarsest grid (h0 = 1/2) has one unknown, which one
+         * sweep solves exactly; a 3-interval coarsest grid has 8 unknowns
+         * and takes 8 sweeps here, enough for the same accuracy */
         for (int k = 1; k < n; ++k)
             for (int j = 1; j < n; ++j)
                 for (int i = 1; i < n; ++i)
                     u[IX(n, i, j, k)] = 0.0;
-        for (int s = 0; s < p->nu0; ++s)
+        const int sweeps = (n == 3 && p->nu0 < 8) ? 8 : p->nu0;
+        for (int s = 0; s < sweeps; ++s)
             nc += sweep_op(n, u, b, p->order, 0);
         return nc;
     }

@@ -20,6 +20,7 @@ MA_COLOR4, MA_COLOR8 = 0, 1
 MA_RESTRICT_FULL, MA_RESTRICT_HALF = 0, 1
 MA_SMOOTHER_AUTO, MA_SMOOTHER_COLOR, MA_SMOOTHER_FUSED = 0, 1, 2
 MA_INIT_POISSON = 1
+MA_INIT_FMG = 2
 
 STATUS_NAMES = {0: "MA_OK", 1: "MA_ERR_ARG", 2: "MA_ERR_OOM", 3: "MA_ERR_DEVICE",
                 4: "MA_ERR_NOT_CONVERGED", 5: "MA_ERR_NONFINITE"}
@@ -88,6 +89,7 @@ _L.ma_sweep.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_lon
 _L.ma_restrict.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.ma_prolong_correct.argtypes = [_vp, _vp, _vp, _vp]
 _L.ma_poisson_init.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)]
+_L.ma_fmg.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_longlong)]
 _L.ma_solve_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                               ctypes.c_int, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_batch_create.argtypes = [ctypes.c_int, _vp, ctypes.POINTER(_vp)]
@@ -100,17 +102,18 @@ _L.ma_batch_add.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_uint,
 _L.ma_batch_tick.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _L.ma_batch_report.argtypes = [_vp, ctypes.c_int, _R]
 _L.ma_batch_remove.argtypes = [_vp, ctypes.c_int]
-for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
-              "ma_restrict", "ma_prolong_correct", "ma_poisson_init", "ma_solve_batch",
-              "ma_batch_create", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
-              "ma_batch_remove"):
+for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
+              "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
+              "ma_fmg", "ma_solve_batch", "ma_batch_create", "ma_batch_add", "ma_batch_tick",
+              "ma_batch_report", "ma_batch_remove"):
     getattr(_L, _name).restype = ctypes.c_int
 
 EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", "ma_destroy",
-           "ma_last_error", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle", "ma_residual", "ma_sweep",
-           "ma_restrict", "ma_prolong_correct", "ma_poisson_init", "ma_solve_batch",
-           "ma_batch_create", "ma_batch_destroy", "ma_batch_last_error", "ma_batch_add",
-           "ma_batch_tick", "ma_batch_report", "ma_batch_remove")
+           "ma_last_error", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
+           "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
+           "ma_fmg", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
+           "ma_batch_last_error", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
+           "ma_batch_remove")
 
 
 def lib() -> ctypes.CDLL:
@@ -200,6 +203,12 @@ def ma_poisson_init(h: int, u: int, f: int) -> int:
     c = ctypes.c_int()
     _check(_L.ma_poisson_init(h, u, f, ctypes.byref(c)), h)
     return c.value
+
+
+def ma_fmg(h: int, u: int, f: int) -> int:
+    nc = ctypes.c_longlong()
+    _check(_L.ma_fmg(h, u, f, ctypes.byref(nc)), h)
+    return nc.value
 
 
 def ma_solve_batch(handles, us, fs, tol: float, flags: int):

@@ -14,8 +14,16 @@ from . import _lib as L
 from .solver import Solver
 
 
-def solve_batch(solvers, us, fs, tol: float | None = None, init_poisson: bool = True):
-    """Solve len(solvers) problems together; returns (status, [report dict])."""
+def _flags(init_poisson, init):
+    if init is None:
+        init = "poisson" if init_poisson else "none"
+    return {"poisson": L.MA_INIT_POISSON, "fmg": L.MA_INIT_FMG, "none": 0}[init]
+
+
+def solve_batch(solvers, us, fs, tol: float | None = None, init_poisson: bool = True,
+                init: str | None = None):
+    """Solve len(solvers) problems together; returns (status, [report dict]).
+    init: "poisson" (default), "fmg" or "none"."""
     if not (len(solvers) == len(us) == len(fs)):
         raise ValueError("solvers, us and fs must have the same length")
     hs, up, fp = [], [], []
@@ -23,7 +31,7 @@ def solve_batch(solvers, us, fs, tol: float | None = None, init_poisson: bool = 
         hs.append(s.handle)
         up.append(s._grid(u))
         fp.append(s._grid(f, name="f"))
-    flags = L.MA_INIT_POISSON if init_poisson else 0
+    flags = _flags(init_poisson, init)
     st, reps = L.ma_solve_batch(hs, up, fp, tol if tol is not None else -1.0, flags)
     return st, [r.as_dict() for r in reps]
 
@@ -49,8 +57,11 @@ class ResidentBatch:
         except Exception:
             pass
 
-    def add(self, solver: Solver, u, f, tol: float | None = None, init_poisson=True) -> int:
-        flags = L.MA_INIT_POISSON if init_poisson else 0
+    def add(self, solver: Solver, u, f, tol: float | None = None, init_poisson=True,
+            init: str | None = None) -> int:
+        """Join a solve; init: "poisson" (default), "fmg" (its FMG-FAS
+        iteration runs now, synchronously) or "none"."""
+        flags = _flags(init_poisson, init)
         slot = L.ma_batch_add(self._b, solver.handle, solver._grid(u), solver._grid(f, name="f"),
                               tol if tol is not None else -1.0, flags)
         self._refs[slot] = (solver, u, f)   # keep the tensors alive while resident

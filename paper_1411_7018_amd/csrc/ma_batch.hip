@@ -54,6 +54,8 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
 {
     if (count < 0 || (count > 0 && (!solvers || !u || !f)))
         return MA_ERR_ARG;
+    if ((flags & MA_INIT_POISSON) && (flags & MA_INIT_FMG))
+        return MA_ERR_ARG;
     for (int i = 0; i < count; ++i)
         if (!solvers[i] || !u[i] || !f[i])
             return MA_ERR_ARG;
@@ -75,6 +77,13 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
         for (int i = 0; i < m; ++i) {
             start_state(st[i], refs[i].s, tol, flags);
             ptr[i] = &st[i];
+            if (flags & MA_INIT_FMG) {
+                // each solve's FMG-FAS iteration runs on its own before the
+                // solves cycle together
+                const ma_status fs = fmg_start(refs[i].s, refs[i].u, refs[i].f, st[i]);
+                if (fs != MA_OK)
+                    return fs;
+            }
         }
         if (eng.reset_counters(-1) != MA_OK)
             return s0->fail(MA_ERR_DEVICE, eng.error());
@@ -100,7 +109,7 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
             x.rep.smooth_seconds = psec;
             x.rep.smooth_launches = plaunch;
             x.rep.smooth_bytes = pbytes;
-            x.rep.nonconvex = (long long)nc[i];
+            x.rep.nonconvex = (long long)nc[i] + x.fmg_nonconvex;
             x.rep.fp64_fallbacks = (long long)fb[i];
             x.rep.seconds = t1 - x.t0;
             if (reps)
@@ -137,6 +146,8 @@ ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, do
 {
     if (!b || !s || !u || !f || !slot_out)
         return MA_ERR_ARG;
+    if ((flags & MA_INIT_POISSON) && (flags & MA_INIT_FMG))
+        return b->fail(MA_ERR_ARG, "MA_INIT_POISSON and MA_INIT_FMG exclude each other");
     int slot = -1;
     for (size_t i = 0; i < b->used.size(); ++i)
         if (!b->used[i]) {
@@ -160,8 +171,17 @@ ma_status ma_batch_add(ma_batch *b, ma_solver *s, double *u, const double *f, do
             (void)b->eng.set(b->refs, b->stream, b->graphs, false);
         return b->fail(st, b->eng.error());
     }
-    b->used[slot] = 1;
     start_state(b->st[slot], s, tol, flags);
+    if (flags & MA_INIT_FMG) {
+        const ma_status fs = fmg_start(s, u, f, b->st[slot]);
+        if (fs != MA_OK) {
+            b->refs[slot] = SolveRef();
+            if (b->any())
+                (void)b->eng.set(b->refs, b->stream, b->graphs, false);
+            return b->fail(fs, s->err);
+        }
+    }
+    b->used[slot] = 1;
     if (b->eng.reset_counters(slot) != MA_OK)
         return b->fail(MA_ERR_DEVICE, b->eng.error());
     *slot_out = slot;
@@ -203,6 +223,7 @@ ma_status ma_batch_tick(ma_batch *b, int *done_out)
             SolveState &x = b->st[i];
             x.rep.nonconvex = (long long)nc[i];
             x.rep.fp64_fallbacks = (long long)fb[i];
+            x.rep.nonconvex += x.fmg_nonconvex;
             x.rep.seconds = t1 - x.t0;
             if (done_out)
                 done_out[i] = x.status == MA_OK ? 1 : 2;

@@ -56,5 +56,11 @@ hipError_t launch_poisson_rhs(hipStream_t st, int n, const double *f, double *R)
 hipError_t launch_copy(hipStream_t st, size_t count, const double *src, double *dst);
 // Copy the Dirichlet layer of src into dst.
 hipError_t launch_copy_boundary(hipStream_t st, int n, const double *src, double *dst);
+// vc (nf/2 intervals) = injection of vf at every coarse node.
+hipError_t launch_inject_all(hipStream_t st, int nf, const double *vf, double *vc);
+// Interior of uf (2 nc intervals) = FMG cubic interpolation of uc.
+hipError_t launch_fmg_interp(hipStream_t st, int nc, const double *uc, double *uf);
+// Interior of u = 0.
+hipError_t launch_zero_interior(hipStream_t st, int n, double *u);
 
 } // namespace mafas

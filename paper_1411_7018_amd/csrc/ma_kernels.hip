@@ -234,6 +234,87 @@ __global__ void k_copy_boundary(const double *__restrict__ src, double *__restri
     }
 }
 
+// Injection onto the grid with half the intervals: every coarse node,
+// boundary included, takes the fine value at the same point.
+__global__ void k_inject_all(const double *__restrict__ vf, double *__restrict__ vc, int nc)
+{
+    const int I = blockIdx.x * RES_BX + threadIdx.x;
+    const int J = blockIdx.y * RES_BY + threadIdx.y;
+    const int K = blockIdx.z;
+    if (I > nc || J > nc)
+        return;
+    const long fy = 2L * nc + 1, cy = nc + 1;
+    vc[I + cy * (J + cy * K)] = vf[2 * I + fy * (2 * J + fy * 2 * K)];
+}
+
+// 1D rule of the FMG interpolation at fine index i (nf = 2 nc intervals):
+// a coarse node is copied; a midpoint takes the cubic Lagrange value through
+// the four nearest coarse nodes (one-sided next to the boundary), or the
+// quadratic value when the coarse grid has only three nodes.
+__device__ __forceinline__ int fmg_rule(int nc, int i, int &first, double w[4])
+{
+    if ((i & 1) == 0) {
+        first = i >> 1;
+        w[0] = 1.0;
+        return 1;
+    }
+    const int m = i >> 1;  // midpoint between coarse m and m + 1
+    if (nc < 3) {
+        first = 0;
+        w[0] = m == 0 ? 0.375 : -0.125;
+        w[1] = 0.75;
+        w[2] = m == 0 ? -0.125 : 0.375;
+        return 3;
+    }
+    if (m == 0) {
+        first = 0;
+        w[0] = 0.3125; w[1] = 0.9375; w[2] = -0.3125; w[3] = 0.0625;
+    } else if (m == nc - 1) {
+        first = nc - 3;
+        w[0] = 0.0625; w[1] = -0.3125; w[2] = 0.9375; w[3] = 0.3125;
+    } else {
+        first = m - 1;
+        w[0] = -0.0625; w[1] = 0.5625; w[2] = 0.5625; w[3] = -0.0625;
+    }
+    return 4;
+}
+
+// FMG interpolation (Algorithm 2, step 4) into the interior of uf: tensor
+// product of the 1D rule, accumulated over (k, j, i) offsets in order.
+__global__ __launch_bounds__(RES_BX *RES_BY) void k_fmg_interp(const double *__restrict__ uc,
+                                                               double *__restrict__ uf, int nc)
+{
+    const int nf = 2 * nc;
+    const int i = 1 + blockIdx.x * RES_BX + threadIdx.x;
+    const int j = 1 + blockIdx.y * RES_BY + threadIdx.y;
+    const int k = 1 + blockIdx.z;
+    if (i > nf - 1 || j > nf - 1)
+        return;
+    int fi, fj, fk;
+    double wi[4], wj[4], wk[4];
+    const int ci = fmg_rule(nc, i, fi, wi);
+    const int cj = fmg_rule(nc, j, fj, wj);
+    const int ck = fmg_rule(nc, k, fk, wk);
+    const long cy = nc + 1;
+    double v = 0.0;
+    for (int c = 0; c < ck; ++c)
+        for (int b = 0; b < cj; ++b)
+            for (int a = 0; a < ci; ++a)
+                v += wk[c] * wj[b] * wi[a] * uc[(fi + a) + cy * ((fj + b) + cy * (fk + c))];
+    uf[i + long(nf + 1) * (j + long(nf + 1) * k)] = v;
+}
+
+// Zero the interior nodes of an (n+1)^3 grid.
+__global__ void k_zero_interior(double *__restrict__ u, int n)
+{
+    const int i = 1 + blockIdx.x * RES_BX + threadIdx.x;
+    const int j = 1 + blockIdx.y * RES_BY + threadIdx.y;
+    const int k = 1 + blockIdx.z;
+    if (i > n - 1 || j > n - 1)
+        return;
+    u[i + long(n + 1) * (j + long(n + 1) * k)] = 0.0;
+}
+
 inline dim3 res_grid(int cnt_x, int cnt_y, int cnt_z)
 {
     return dim3((cnt_x + RES_BX - 1) / RES_BX, (cnt_y + RES_BY - 1) / RES_BY, cnt_z);
@@ -339,6 +420,31 @@ hipError_t launch_copy(hipStream_t st, size_t count, const double *src, double *
     if (count == 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3((count + 255) / 256), dim3(256), 0, st, src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject_all(hipStream_t st, int nf, const double *vf, double *vc)
+{
+    const int nc = nf / 2;
+    hipLaunchKernelGGL(k_inject_all, res_grid(nc + 1, nc + 1, nc + 1), dim3(RES_BX, RES_BY), 0, st,
+                       vf, vc, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fmg_interp(hipStream_t st, int nc, const double *uc, double *uf)
+{
+    const int nf = 2 * nc;
+    hipLaunchKernelGGL(k_fmg_interp, res_grid(nf - 1, nf - 1, nf - 1), dim3(RES_BX, RES_BY), 0, st,
+                       uc, uf, nc);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_interior(hipStream_t st, int n, double *u)
+{
+    if (n < 2)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_zero_interior, res_grid(n - 1, n - 1, n - 1), dim3(RES_BX, RES_BY), 0, st,
+                       u, n);
     return hipGetLastError();
 }
 

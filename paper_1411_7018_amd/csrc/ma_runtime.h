@@ -71,6 +71,10 @@ struct ma_solver {
     std::vector<mafas::MixedLevel> mx;
     std::string err;
     mafas::Engine *eng = nullptr;         // batch-of-one engine of ma_solve / ma_vcycle
+    // FMG: solvers that alias this hierarchy from level l down (no storage
+    // of their own), so that a V-cycle rooted at level l runs through the
+    // same engine code as the finest one
+    std::vector<ma_solver *> views;
 
     ~ma_solver();
     ma_status fail(ma_status st, const std::string &msg);
@@ -82,6 +86,11 @@ struct ma_solver {
     ma_status smooth(int l, double *u, const double *F, int count, int op);
     ma_status finish_norm(int n, double *l2);
     ma_status own_engine(mafas::Engine **out, double *u, const double *f);
+    ma_solver *view(int l);
+    // One FMG-FAS iteration (Algorithm 2) on u, whose interior is not read;
+    // adds its non-certified updates, point updates and algorithmic bytes.
+    ma_status fmg(double *u, const double *f, long long *nonconvex, double *updates,
+                  double *bytes);
     ma_status mixed_allocate();
     void mixed_release();
 };
@@ -98,7 +107,15 @@ struct SolveState {
     std::string err;
     ma_report rep{};
     double t0 = 0.0;        // start time (seconds)
+    bool fmg = false;       // started by one FMG-FAS iteration: res0 is the
+                            // residual of the zero-interior start, and the
+                            // FMG iteration is the first cycle
+    long long fmg_nonconvex = 0;
 };
+
+// The FMG start of a solve (Section 4 protocol): zero the interior of u, take
+// r^0 there, run one FMG-FAS iteration; st then continues at MAIN0.
+ma_status fmg_start(ma_solver *s, double *u, const double *f, SolveState &st);
 
 // One scheduling step over the engine's slots: the entry residuals of solves
 // starting a phase, then one tick of every solve that is cycling (Poisson

@@ -220,13 +220,17 @@ ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigne
         return MA_ERR_ARG;
     if (!u || !f)
         return s->fail(MA_ERR_ARG, "u and f must be device pointers");
-    Engine *E = nullptr;
-    MA_TRY(s->own_engine(&E, u, f));
+    if ((flags & MA_INIT_POISSON) && (flags & MA_INIT_FMG))
+        return s->fail(MA_ERR_ARG, "MA_INIT_POISSON and MA_INIT_FMG exclude each other");
     SolveState st;
     st.tol = tol > 0.0 ? tol : s->p.tol;
     st.phase = (flags & MA_INIT_POISSON) ? SolveState::INIT0 : SolveState::MAIN0;
     st.t0 = now_seconds();
     std::memset(&st.rep, 0, sizeof(st.rep));
+    if (flags & MA_INIT_FMG)
+        MA_TRY(fmg_start(s, u, f, st));
+    Engine *E = nullptr;
+    MA_TRY(s->own_engine(&E, u, f));
     if (E->reset_counters(0) != MA_OK)
         return s->fail(MA_ERR_DEVICE, E->error());
     std::vector<SolveState *> states{&st};
@@ -236,7 +240,7 @@ ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigne
     }
     std::vector<unsigned long long> nc, fb;
     if (E->read_counters(nc, fb) == MA_OK) {
-        st.rep.nonconvex = (long long)nc[0];
+        st.rep.nonconvex = (long long)nc[0] + st.fmg_nonconvex;
         st.rep.fp64_fallbacks = (long long)fb[0];
     }
     if (s->p.profile) {
@@ -330,6 +334,19 @@ ma_status ma_prolong_correct(ma_solver *s, double *u, const double *u_c, const d
     return MA_OK;
 }
 
+ma_status ma_fmg(ma_solver *s, double *u, const double *f, long long *nonconvex_host)
+{
+    if (!s)
+        return MA_ERR_ARG;
+    if (!u || !f)
+        return s->fail(MA_ERR_ARG, "u and f must be device pointers");
+    long long nc = 0;
+    MA_TRY(s->fmg(u, f, &nc, nullptr, nullptr));
+    if (nonconvex_host)
+        *nonconvex_host = nc;
+    return MA_OK;
+}
+
 ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_host)
 {
     if (!s)
@@ -362,6 +379,8 @@ ma_status ma_poisson_init(ma_solver *s, double *u, const double *f, int *cycles_
 // ---------------------------------------------------------------------------
 ma_solver::~ma_solver()
 {
+    for (ma_solver *v : views)
+        delete v;
     delete eng;
     for (double *q : owned)
         (void)hipFree(q);
@@ -494,6 +513,97 @@ ma_status ma_solver::own_engine(Engine **out, double *u, const double *f)
     return MA_OK;
 }
 
+// A solver over levels l..L-1 of this one: it owns nothing (its level
+// arrays are this solver's), and its level 0 takes u and F from the caller
+// of its engine (here: this solver's level-l u and b).
+ma_solver *ma_solver::view(int l)
+{
+    if (views.size() < lv.size())
+        views.resize(lv.size(), nullptr);
+    if (!views[l]) {
+        ma_solver *v = new ma_solver();
+        v->p = p;
+        v->p.n = lv[l].n;
+        v->p.precision = MA_FP64;
+        v->p.profile = 0;
+        v->lv.assign(lv.begin() + l, lv.end());
+        v->lv[0].u = v->lv[0].b = v->lv[0].w = nullptr;
+        views[l] = v;
+    }
+    views[l]->stream = stream;
+    views[l]->p.coarse_n = p.coarse_n;
+    views[l]->p.max_blocks = p.max_blocks;
+    views[l]->p.strip_rows = p.strip_rows;
+    return views[l];
+}
+
+// Algorithm 2 unrolled: inject f (b_H := injection of b_h) and the
+// Dirichlet data of u down the hierarchy; on the coarsest grid start from
+// zero and sweep nu0 times; then on the way up interpolate (cubic FMG
+// interpolation) and run one FAS V-cycle per level.
+ma_status ma_solver::fmg(double *u, const double *f, long long *nonconvex, double *updates,
+                         double *bytes)
+{
+    const int L = int(lv.size());
+    auto U = [&](int l) { return l == 0 ? u : lv[l].u; };
+    auto B = [&](int l) -> const double * { return l == 0 ? f : lv[l].b; };
+    for (int l = 1; l < L; ++l) {
+        MA_HIP(this, launch_inject_all(stream, lv[l - 1].n, B(l - 1), lv[l].b));
+        MA_HIP(this, launch_inject_all(stream, lv[l - 1].n, U(l - 1), lv[l].u));
+    }
+    // coarsest grid: zero inside, then an approximate solve -- nu0 sweeps
+    // solve a one-unknown grid exactly; a 3-interval grid (8 unknowns)
+    // takes 8 sweeps
+    const int c = L - 1;
+    const int csweeps = (lv[c].n == 3 && p.nu0 < 8) ? 8 : p.nu0;
+    MA_HIP(this, launch_zero_interior(stream, lv[c].n, U(c)));
+    MA_HIP(this, launch_fill_u64(stream, 1, 0ull, dcount));
+    MA_TRY(smooth(c, U(c), B(c), csweeps, OP_MA));
+    MA_HIP(this, hipMemcpyAsync(hpin_u64, dcount, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, stream));
+    MA_HIP(this, hipStreamSynchronize(stream));
+    long long nc = (long long)hpin_u64[0];
+    double up = double(csweeps) * interior(lv[c].n), by = 24.0 * up;
+    std::vector<double> nrm;
+    std::vector<unsigned long long> cnt, fb;
+    for (int l = L - 2; l >= 0; --l) {
+        MA_HIP(this, launch_fmg_interp(stream, lv[l + 1].n, U(l + 1), U(l)));
+        ma_solver *v = l == 0 ? this : view(l);
+        Engine *E = nullptr;
+        MA_TRY(v->own_engine(&E, U(l), B(l)));
+        if (E->reset_counters(0) != MA_OK || E->tick(Engine::MODE_MA, {1}, nrm) != MA_OK ||
+            E->read_counters(cnt, fb) != MA_OK)
+            return fail(MA_ERR_DEVICE, E->error());
+        nc += (long long)cnt[0];
+        double tu, tb;
+        E->tick_cost(Engine::MODE_MA, 0, &tu, &tb);
+        up += tu;
+        by += tb;
+    }
+    if (nonconvex)
+        *nonconvex += nc;
+    if (updates)
+        *updates += up;
+    if (bytes)
+        *bytes += by;
+    return MA_OK;
+}
+
+ma_status mafas::fmg_start(ma_solver *s, double *u, const double *f, SolveState &st)
+{
+    MA_HIP(s, launch_zero_interior(s->stream, s->p.n, u));
+    Engine *E = nullptr;
+    MA_TRY(s->own_engine(&E, u, f));
+    std::vector<double> nrm;
+    if (E->norms_only(Engine::MODE_MA, {1}, nrm) != MA_OK)
+        return s->fail(MA_ERR_DEVICE, E->error());
+    st.rep.res0 = st.rep.res = nrm[0];
+    MA_TRY(s->fmg(u, f, &st.fmg_nonconvex, &st.rep.point_updates, &st.rep.alg_bytes));
+    st.fmg = true;
+    st.phase = SolveState::MAIN0;
+    return MA_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Per-solve phase machine shared by ma_solve, ma_solve_batch and ma_batch.
 // ---------------------------------------------------------------------------
@@ -565,13 +675,34 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 SolveState *st = states[i];
+                const int maxc = eng.ref(i).s->p.max_cycles;
+                if (st->fmg) {
+                    // the FMG-FAS iteration is the first cycle; res0 is the
+                    // residual of the zero-interior start
+                    ma_report &r = st->rep;
+                    r.cycles = 1;
+                    r.outer = eng.mixed() ? 1 : 0;
+                    r.res = r.history[0] = nrm[i];
+                    r.rel_res = r.res0 > 0.0 ? r.res / r.res0 : 0.0;
+                    if (!std::isfinite(nrm[i]))
+                        finish(st, MA_ERR_NONFINITE, "residual after FMG is not finite");
+                    else if (r.res <= st->tol * r.res0) {
+                        r.converged = 1;
+                        finish(st, MA_OK, "");
+                    } else if (maxc <= 1) {
+                        finish(st, MA_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
+                    } else {
+                        st->phase = SolveState::MAIN;
+                    }
+                    continue;
+                }
                 st->rep.res0 = st->rep.res = nrm[i];
                 if (!std::isfinite(nrm[i]))
                     finish(st, MA_ERR_NONFINITE, "initial residual is not finite");
                 else if (nrm[i] == 0.0) {
                     st->rep.converged = 1;
                     finish(st, MA_OK, "");
-                } else if (eng.ref(i).s->p.max_cycles == 0) {
+                } else if (maxc == 0) {
                     finish(st, MA_ERR_NOT_CONVERGED, "max_cycles is 0");
                 } else {
                     st->phase = SolveState::MAIN;

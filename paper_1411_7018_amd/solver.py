@@ -90,8 +90,14 @@ class Solver:
             raise ValueError(f"{name} must be contiguous with shape {(n + 1,) * 3}")
         return t.data_ptr()
 
-    def solve(self, u, f, tol: float | None = None, init_poisson: bool = True) -> dict:
-        flags = L.MA_INIT_POISSON if init_poisson else 0
+    def solve(self, u, f, tol: float | None = None, init_poisson: bool = True,
+              init: str | None = None) -> dict:
+        """init: "poisson" (default), "fmg" (Section 4 protocol: one FMG-FAS
+        iteration as the first cycle) or "none"; init_poisson=False is the
+        same as init="none"."""
+        if init is None:
+            init = "poisson" if init_poisson else "none"
+        flags = {"poisson": L.MA_INIT_POISSON, "fmg": L.MA_INIT_FMG, "none": 0}[init]
         rep = L.ma_solve(self.handle, self._grid(u), self._grid(f, name="f"),
                          tol if tol is not None else -1.0, flags)
         return rep.as_dict()
@@ -118,6 +124,10 @@ class Solver:
         nc = self.n // 2
         L.ma_prolong_correct(self.handle, self._grid(u), self._grid(uc, nc, "uc"),
                              self._grid(wc, nc, "wc"))
+
+    def fmg(self, u, f) -> int:
+        """One FMG-FAS iteration (Algorithm 2); returns non-certified updates."""
+        return L.ma_fmg(self.handle, self._grid(u), self._grid(f, name="f"))
 
     def poisson_init(self, u, f) -> int:
         return L.ma_poisson_init(self.handle, self._grid(u), self._grid(f, name="f"))

@@ -72,7 +72,7 @@ def _np_fmg(u, f, p, coarsest):
     n = u.shape[0] - 1
     if n == coarsest:
         u[1:-1, 1:-1, 1:-1] = 0.0
-        for _ in range(p.nu0):
+        for _ in range(8 if n == 3 else p.nu0):
             oracle.sweep(u, f, p.order)
         return
     uc, fc = oracle.inject(u), oracle.inject(f)
@@ -133,3 +133,17 @@ def test_fmg_reaches_discretization_accuracy(order, factor, min_order):
         errs.append(e_fmg)
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > min_order)
+
+
+@pytest.mark.parametrize("n", [24, 48])
+def test_fmg_on_three_interval_coarsest_grid(n):
+    """Hierarchies ending on a 3-interval grid (8 unknowns): the FMG start
+    is at discretization accuracy and the solve converges (one sweep there
+    would leave a non-convex start from which the V-cycles diverge)."""
+    p = P.exp_cos(n, seed=5)
+    u = P.initial_guess(p)
+    oracle.fmg(u, p.f)
+    assert np.abs(u - p.u_exact).max() < 5e-4
+    v = P.initial_guess(p)
+    st, rep, _ = oracle.solve(v, p.f, oracle.params(init="fmg", tol=1e-9))
+    assert st == 0 and rep.cycles <= 8
