@@ -40,11 +40,16 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {("quadratic129", "fp64"): 36519302}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
-    # name: (kind, n, seed, tol)
-    "quadratic129": ("quadratic", 128, 1001, 1e-8),
-    "example4_17": ("example4", 16, 0, 1e-10),
-    "expcos257": ("exp_cos", 256, 3001, 1e-8),
-    "expcos385": ("exp_cos", 384, 5001, 1e-8),
+    # name: (kind, n, seed, tol, start)
+    "quadratic129": ("quadratic", 128, 1001, 1e-8, "poisson"),
+    "example4_17": ("example4", 16, 0, 1e-10, "poisson"),
+    "expcos257": ("exp_cos", 256, 3001, 1e-8, "poisson"),
+    "expcos385": ("exp_cos", 384, 5001, 1e-8, "poisson"),
+    # Section 4 protocol (FMG-FAS start, tolerance 1e-6) on Examples 4-7
+    "example4_129_fmg": ("example4", 128, 0, 1e-6, "fmg"),
+    "example5_129_fmg": ("example5", 128, 0, 1e-6, "fmg"),
+    "example6_129_fmg": ("example6", 128, 0, 1e-6, "fmg"),
+    "example7_129_fmg": ("example7", 128, 0, 1e-6, "fmg"),
 }
 WORKLOADS = sorted(SINGLE) + ["batch64", "served"]
 
@@ -58,9 +63,9 @@ def parse():
     ap.add_argument("--workload", default="quadratic129", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, except batch64 (mixed)")
-    ap.add_argument("--init", default="poisson", choices=["poisson", "fmg"],
-                    help="single solves: Poisson initial guess (default) or the Section 4 "
-                         "protocol (one FMG-FAS iteration as the first cycle)")
+    ap.add_argument("--init", default=None, choices=["poisson", "fmg"],
+                    help="single solves: Poisson initial guess or the Section 4 protocol "
+                         "(one FMG-FAS iteration as the first cycle); default per workload")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuned", default=None,
                     help="coarse_n,max_blocks[,strip_rows] to use instead of running the "
@@ -89,7 +94,7 @@ def roofline(reps, traffic=None):
     return out
 
 
-def cpu_baseline(kind, n, seed, tol):
+def cpu_baseline(kind, n, seed, tol, init="poisson"):
     """The oracle (serial C, one core) on a bounded sample of the workload:
     the full solve when it fits in ~30 s, else V-cycles on it for ~20 s."""
     import oracle
@@ -99,12 +104,12 @@ def cpu_baseline(kind, n, seed, tol):
     u = P.initial_guess(p)
     if n <= 128:
         t0 = time.perf_counter()
-        st, rep, _ = oracle.solve(u, p.f, oracle.params(tol=tol))
+        st, rep, _ = oracle.solve(u, p.f, oracle.params(tol=tol, init=init))
         dt = time.perf_counter() - t0
+        start = (f"{rep.init_cycles} Poisson + " if init == "poisson" else "FMG-FAS + ")
         return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
                 "sample": f"one full solve of the same {n + 1}^3 problem "
-                          f"({rep.init_cycles} Poisson + {rep.cycles} FAS V(2,2) cycles, "
-                          f"{dt:.1f} s)"}
+                          f"({start}{rep.cycles} cycles in all, {dt:.1f} s)"}
     oracle.poisson_init(u, p.f, oracle.params())
     t0 = time.perf_counter()
     cyc = 0
@@ -168,7 +173,8 @@ def run_single(args, precision):
 
     from paper_1411_7018_amd import Solver, problems as P
 
-    kind, n, seed, tol = SINGLE[args.workload]
+    kind, n, seed, tol, start = SINGLE[args.workload]
+    init = args.init or start
     steps = args.steps or 20
     warmup = 3 if args.warmup is None else args.warmup
     prob = P.make(kind, n, seed)
@@ -181,7 +187,7 @@ def run_single(args, precision):
 
     def step():
         u.copy_(u_init)
-        return s.solve(u, f, tol=tol, init=args.init)
+        return s.solve(u, f, tol=tol, init=init)
 
     for _ in range(warmup):
         step()
@@ -199,17 +205,17 @@ def run_single(args, precision):
     out = base_line(args, steps / elapsed, steps, warmup, elapsed, lat, precision)
     out["config"] = {
         "workload": f"{kind} {n + 1}^3 single solve, seed {seed}, tol {tol:g}, "
-                    + ("Poisson initial guess" if args.init == "poisson" else
+                    + ("Poisson initial guess" if init == "poisson" else
                        "FMG-FAS start (r0 of the zero-interior start)")
                     + f", FAS V(2,2), 4-colour nonlinear GS, {precision}",
-        "n": n, "tol": tol, "precision": precision, "init": args.init,
+        "n": n, "tol": tol, "precision": precision, "init": init,
         "tuned": tune_note(choice)}
     out.update({"updates_per_s": sum(r["point_updates"] for r in reps) / elapsed,
                 "cycles": last["cycles"], "init_cycles": last["init_cycles"],
                 "rel_res": last["rel_res"], "max_err_vs_exact": err,
                 "roofline": roofline(reps, TRAFFIC.get((args.workload, precision)))})
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(kind, n, seed, tol)
+        out["cpu_baseline"] = cpu_baseline(kind, n, seed, tol, init)
     return out
 
 

@@ -14,6 +14,8 @@ flattening puts x fastest.
 
 Workloads:
   * ``example4``      -- Example 4 of Section 4 (u = exp(|x|^2/2)).
+  * ``example5`` .. ``example7`` -- Examples 5-7 of Section 4 (Example 5's
+                         (0, pi)^3 restated on the unit cube).
   * ``quadratic``     -- u = x^T A x / 2 + b^T x with a seeded SPD A whose
                          eigenvalues lie in [0.5, 2] and b ~ U[-1, 1]^3;
                          centred differences are exact on quadratics.
@@ -31,7 +33,8 @@ import math
 import numpy as np
 
 __all__ = [
-    "Problem", "grid", "example4", "quadratic", "exp_cos", "make", "make_device",
+    "Problem", "grid", "example4", "example5", "example6", "example7", "quadratic", "exp_cos",
+    "make", "make_device",
     "figure1_error", "initial_guess", "batch_specs", "arrival_trace",
     "SERVE_SIZES", "SERVE_WEIGHTS", "BATCH_SIZES",
 ]
@@ -145,9 +148,54 @@ def exp_cos(n: int, seed: int = 0) -> Problem:
     return Problem("exp_cos", n, f, u)
 
 
+def example5(n: int) -> Problem:
+    """Example 5 on (0, pi)^3: u = -sum sin(x_i) + |x|^2/2, whose Hessian is
+    diag(1 + sin x_i), f = prod(1 + sin x_i).  Stated on the unit cube by
+    x = pi xi: the grid values of u are those of u(pi xi), and since every
+    discrete second difference on the (0, pi)^3 grid is pi^-2 times the one
+    on the unit-cube grid, the discrete equations are those of the unit
+    cube with f scaled by pi^6 (the Newton roots scale by pi^2 and the
+    updates u_p + sigma h^2 / 2 coincide)."""
+    x, y, z = grid(n)
+    X, Y, Z = math.pi * x, math.pi * y, math.pi * z
+    u = -np.sin(X) - np.sin(Y) - np.sin(Z) + 0.5 * (X * X + Y * Y + Z * Z)
+    f = math.pi ** 6 * (np.sin(X) + 1.0) * (np.sin(Y) + 1.0) * (np.sin(Z) + 1.0)
+    return Problem("example5", n, f, u)
+
+
+def example6(n: int) -> Problem:
+    """Example 6: u = |x|^{3/2} / 3, f = |x|^{-3/2} / 16, singular at the
+    origin (a boundary node, where f is never read and is set to 0)."""
+    x, y, z = grid(n)
+    r2 = x * x + y * y + z * z
+    u = r2 ** 0.75 / 3.0
+    with np.errstate(divide="ignore"):
+        f = np.where(r2 > 0.0, r2 ** -0.75 / 16.0, 0.0)
+    return Problem("example6", n, f, u)
+
+
+def example7(n: int) -> Problem:
+    """Example 7: u = -sqrt(3 - |x|^2), f = 3 (3 - |x|^2)^{-5/2}; the
+    gradient is unbounded at the corner (1, 1, 1) (a boundary node, where f
+    is never read and is set to 0)."""
+    x, y, z = grid(n)
+    q = 3.0 - (x * x + y * y + z * z)
+    q = np.maximum(q, 0.0)
+    u = -np.sqrt(q)
+    with np.errstate(divide="ignore"):
+        f = np.where(q > 0.0, 3.0 * q ** -2.5, 0.0)
+    return Problem("example7", n, f, u)
+
+
 def make(kind: str, n: int, seed: int = 0) -> Problem:
     if kind == "example4":
         return example4(n)
+    if kind == "example5":
+        return example5(n)
+    if kind == "example6":
+        return example6(n)
+    if kind == "example7":
+        return example7(n)
     if kind == "quadratic":
         return quadratic(n, seed)
     if kind == "exp_cos":
@@ -215,6 +263,17 @@ def make_device(kind: str, n: int, seed: int = 0, device="cuda", exact: bool = F
     if kind == "example4":
         u = torch.exp(0.5 * r2)
         f = (1.0 + r2) * torch.exp(1.5 * r2)
+    elif kind == "example5":
+        X, Y, Z = math.pi * x, math.pi * y, math.pi * z
+        u = -torch.sin(X) - torch.sin(Y) - torch.sin(Z) + 0.5 * (X * X + Y * Y + Z * Z)
+        f = math.pi ** 6 * (torch.sin(X) + 1.0) * (torch.sin(Y) + 1.0) * (torch.sin(Z) + 1.0)
+    elif kind == "example6":
+        u = r2 ** 0.75 / 3.0
+        f = torch.where(r2 > 0.0, r2.clamp_min(1e-300) ** -0.75 / 16.0, torch.zeros_like(r2))
+    elif kind == "example7":
+        q = (3.0 - r2).clamp_min(0.0)
+        u = -torch.sqrt(q)
+        f = torch.where(q > 0.0, 3.0 * q.clamp_min(1e-300) ** -2.5, torch.zeros_like(q))
     elif kind == "quadratic":
         a, b = _quadratic_params(seed)
         u = (0.5 * (a[0, 0] * x * x + a[1, 1] * y * y + a[2, 2] * z * z)
