@@ -51,7 +51,9 @@ SINGLE = {
     "example6_129_fmg": ("example6", 128, 0, 1e-6, "fmg"),
     "example7_129_fmg": ("example7", 128, 0, 1e-6, "fmg"),
 }
-WORKLOADS = sorted(SINGLE) + ["batch64", "served"]
+# the standalone Gauss-Seidel solver from 1.01 u to 1e-6 (Table 3 protocol)
+GS = {"gs_example4_33": ("example4", 32, 1e-6)}
+WORKLOADS = sorted(SINGLE) + sorted(GS) + ["batch64", "served"]
 
 
 def parse():
@@ -219,6 +221,45 @@ def run_single(args, precision):
     return out
 
 
+def run_gs(args, precision):
+    import torch
+
+    from paper_1411_7018_amd import Solver, problems as P
+
+    kind, n, tol = GS[args.workload]
+    steps = args.steps or 5
+    warmup = 1 if args.warmup is None else args.warmup
+    prob = P.make(kind, n)
+    u0 = torch.from_numpy(P.initial_guess(prob, 1.01 * prob.u_exact)).cuda()
+    f = torch.from_numpy(prob.f).cuda()
+    u = torch.empty_like(u0)
+    s = Solver(n, precision=precision)
+
+    def step():
+        u.copy_(u0)
+        return s.gs_solve(u, f, tol=tol)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, reps = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        reps.append(step())
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = base_line(args, steps / elapsed, steps, warmup, elapsed, lat, "fp64")
+    out["config"] = {"workload": f"standalone nonlinear Gauss-Seidel (4-colour) on {kind} "
+                                 f"{n + 1}^3 from 1.01 u to relative residual {tol:g}",
+                     "n": n, "tol": tol}
+    out.update({"sweeps": reps[-1]["cycles"], "rel_res": reps[-1]["rel_res"],
+                "max_err_vs_exact": float(np.abs(u.cpu().numpy() - prob.u_exact).max()),
+                "updates_per_s": sum(r["point_updates"] for r in reps) / elapsed})
+    return out
+
+
 def run_batch(args, precision):
     import torch
 
@@ -334,6 +375,8 @@ def main():
     precision = args.precision or ("mixed" if args.workload == "batch64" else "fp64")
     if args.workload in SINGLE:
         out = run_single(args, precision)
+    elif args.workload in GS:
+        out = run_gs(args, precision)
     elif args.workload == "batch64":
         out = run_batch(args, precision)
     else:

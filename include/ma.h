@@ -212,6 +212,17 @@ ma_status ma_prolong_correct(ma_solver *s, double *u, const double *u_c, const d
  * NULL) receives the non-certified updates.  Synchronises the stream. */
 ma_status ma_fmg(ma_solver *s, double *u, const double *f, long long *nonconvex_host);
 
+/* The standalone nonlinear Gauss-Seidel solver the paper compares against
+ * (Section 4, the Gauss-Seidel halves of Tables 3 and 5-7): sweeps of the
+ * smoother on the finest grid alone, u's interior as the start, until the
+ * relative discrete L2 residual is <= tol (tol <= 0: the solver's tol) or
+ * max_sweeps ran (MA_ERR_NOT_CONVERGED, report still filled).  The residual
+ * is checked after every sweep, as in Section 4.  rep (may be NULL):
+ * cycles = sweeps, res0, res, rel_res, history of the first 64 sweeps,
+ * nonconvex, point_updates, alg_bytes, seconds.  Synchronises the stream. */
+ma_status ma_gs_solve(ma_solver *s, double *u, const double *f, double tol, int max_sweeps,
+                      ma_report *rep);
+
 /* The MA_INIT_POISSON initial guess alone: linear V-cycles on
  * Lap_h u = 3 f^{1/3} until the relative linear residual is <= init_tol or
  * init_max_cycles ran.  cycles_host (may be NULL) receives the cycle count. */

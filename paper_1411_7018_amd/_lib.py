@@ -90,6 +90,7 @@ _L.ma_restrict.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _L.ma_prolong_correct.argtypes = [_vp, _vp, _vp, _vp]
 _L.ma_poisson_init.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int)]
 _L.ma_fmg.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_longlong)]
+_L.ma_gs_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _R]
 _L.ma_solve_batch.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                               ctypes.c_int, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_batch_create.argtypes = [ctypes.c_int, _vp, ctypes.POINTER(_vp)]
@@ -104,14 +105,15 @@ _L.ma_batch_report.argtypes = [_vp, ctypes.c_int, _R]
 _L.ma_batch_remove.argtypes = [_vp, ctypes.c_int]
 for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
               "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
-              "ma_fmg", "ma_solve_batch", "ma_batch_create", "ma_batch_add", "ma_batch_tick",
+              "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_add",
+              "ma_batch_tick",
               "ma_batch_report", "ma_batch_remove"):
     getattr(_L, _name).restype = ctypes.c_int
 
 EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", "ma_destroy",
            "ma_last_error", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
            "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
-           "ma_fmg", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
+           "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
            "ma_batch_last_error", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
            "ma_batch_remove")
 
@@ -209,6 +211,14 @@ def ma_fmg(h: int, u: int, f: int) -> int:
     nc = ctypes.c_longlong()
     _check(_L.ma_fmg(h, u, f, ctypes.byref(nc)), h)
     return nc.value
+
+
+def ma_gs_solve(h: int, u: int, f: int, tol: float, max_sweeps: int) -> ma_report:
+    rep = ma_report()
+    st = _L.ma_gs_solve(h, u, f, float(tol), int(max_sweeps), ctypes.byref(rep))
+    if st != MA_OK:
+        raise MAError(st, ma_last_error(h), rep.as_dict())
+    return rep
 
 
 def ma_solve_batch(handles, us, fs, tol: float, flags: int):

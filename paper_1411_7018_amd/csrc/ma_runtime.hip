@@ -334,6 +334,66 @@ ma_status ma_prolong_correct(ma_solver *s, double *u, const double *u_c, const d
     return MA_OK;
 }
 
+ma_status ma_gs_solve(ma_solver *s, double *u, const double *f, double tol, int max_sweeps,
+                      ma_report *rep)
+{
+    if (!s)
+        return MA_ERR_ARG;
+    if (!u || !f || max_sweeps < 0)
+        return s->fail(MA_ERR_ARG, "u, f must be device pointers and max_sweeps >= 0");
+    const double t0 = now_seconds();
+    const int n = s->p.n;
+    const double target = tol > 0.0 ? tol : s->p.tol;
+    ma_report r;
+    std::memset(&r, 0, sizeof(r));
+    auto norm = [&](double *l2) -> ma_status {
+        MA_HIP(s, launch_residual(s->stream, OP_MA, n, u, f, nullptr, s->partials));
+        return s->finish_norm(n, l2);
+    };
+    MA_TRY(norm(&r.res0));
+    r.res = r.res0;
+    MA_HIP(s, launch_fill_u64(s->stream, 1, 0ull, s->dcount));
+    ma_status st = MA_ERR_NOT_CONVERGED;
+    if (!std::isfinite(r.res0)) {
+        st = MA_ERR_NONFINITE;
+    } else if (r.res0 == 0.0) {
+        st = MA_OK;
+    } else {
+        const double in = interior(n);
+        while (r.cycles < max_sweeps) {
+            MA_TRY(s->smooth(0, u, f, 1, OP_MA));
+            r.cycles += 1;
+            r.point_updates += in;
+            r.alg_bytes += 24.0 * in + 16.0 * in;   // sweep + residual check
+            MA_TRY(norm(&r.res));
+            if (r.cycles <= 64)
+                r.history[r.cycles - 1] = r.res;
+            if (!std::isfinite(r.res)) {
+                st = MA_ERR_NONFINITE;
+                break;
+            }
+            if (r.res <= target * r.res0) {
+                st = MA_OK;
+                break;
+            }
+        }
+    }
+    r.rel_res = r.res0 > 0.0 ? r.res / r.res0 : 0.0;
+    r.converged = st == MA_OK;
+    MA_HIP(s, hipMemcpyAsync(s->hpin_u64, s->dcount, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s->stream));
+    MA_HIP(s, hipStreamSynchronize(s->stream));
+    r.nonconvex = (long long)s->hpin_u64[0];
+    r.seconds = now_seconds() - t0;
+    if (rep)
+        *rep = r;
+    if (st == MA_ERR_NOT_CONVERGED)
+        return s->fail(st, "max_sweeps reached before the tolerance");
+    if (st == MA_ERR_NONFINITE)
+        return s->fail(st, "residual is not finite");
+    return MA_OK;
+}
+
 ma_status ma_fmg(ma_solver *s, double *u, const double *f, long long *nonconvex_host)
 {
     if (!s)

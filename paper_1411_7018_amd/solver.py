@@ -125,6 +125,12 @@ class Solver:
         L.ma_prolong_correct(self.handle, self._grid(u), self._grid(uc, nc, "uc"),
                              self._grid(wc, nc, "wc"))
 
+    def gs_solve(self, u, f, tol: float | None = None, max_sweeps: int = 100000) -> dict:
+        """The standalone nonlinear Gauss-Seidel solver (no multigrid)."""
+        rep = L.ma_gs_solve(self.handle, self._grid(u), self._grid(f, name="f"),
+                            tol if tol is not None else -1.0, max_sweeps)
+        return rep.as_dict()
+
     def fmg(self, u, f) -> int:
         """One FMG-FAS iteration (Algorithm 2); returns non-certified updates."""
         return L.ma_fmg(self.handle, self._grid(u), self._grid(f, name="f"))
