@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ma_oracle.c")
+_SRC2 = os.path.join(_HERE, "ma2_oracle.c")    # the 2D variant (oracle.ma2)
 _LIB = os.path.join(_HERE, "libmaoracle.so")
 
 ORDER_4C, ORDER_8C, ORDER_LEX = 0, 1, 2
@@ -26,10 +27,10 @@ _ORDERS = {"4c": 0, "color4": 0, "8c": 1, "color8": 1, "lex": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile ma_oracle.c into libmaoracle.so next to it."""
+    """Compile ma_oracle.c and ma2_oracle.c into libmaoracle.so next to them."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11",
-               "-D_GNU_SOURCE", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-D_GNU_SOURCE", "-Wall", "-o", _LIB + ".tmp", _SRC, _SRC2, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB

@@ -308,3 +308,50 @@ def make_device(kind: str, n: int, seed: int = 0, device="cuda", exact: bool = F
     if exact:
         return u0, f, u
     return u0, f
+
+
+# ---------------------------------------------------------------------------
+# 2D variant (u_xx u_yy - u_xy^2 = f on the unit square), Examples 1-3 of
+# Section 4.  Arrays (n+1, n+1) indexed [j, i], x fastest.
+# ---------------------------------------------------------------------------
+def grid2(n: int):
+    if n < 2:
+        raise ValueError("n must be >= 2")
+    t = np.arange(n + 1, dtype=np.float64) / n
+    y, x = np.meshgrid(t, t, indexing="ij")
+    return x, y
+
+
+def example2d(number: int, n: int) -> Problem:
+    """Example 1: u = exp(|x|^2/2), f = (1 + |x|^2) exp(|x|^2);
+    Example 2: u = (2 sqrt 2 / 3) |x|^{3/2}, f = 1/|x| (singular at the
+    origin, a boundary node where f is never read and is set to 0);
+    Example 3: u = -sqrt(2 - |x|^2), f = 2 / (2 - |x|^2)^2 (unbounded
+    gradient at the corner (1, 1), where f is set to 0)."""
+    x, y = grid2(n)
+    r2 = x * x + y * y
+    if number == 1:
+        u = np.exp(0.5 * r2)
+        f = (1.0 + r2) * np.exp(r2)
+    elif number == 2:
+        u = (2.0 * math.sqrt(2.0) / 3.0) * r2 ** 0.75
+        with np.errstate(divide="ignore"):
+            f = np.where(r2 > 0.0, 1.0 / np.sqrt(np.where(r2 > 0.0, r2, 1.0)), 0.0)
+    elif number == 3:
+        q = np.maximum(2.0 - r2, 0.0)
+        u = -np.sqrt(q)
+        with np.errstate(divide="ignore"):
+            f = np.where(q > 0.0, 2.0 / np.where(q > 0.0, q, 1.0) ** 2, 0.0)
+    else:
+        raise ValueError("2D examples are 1, 2, 3")
+    return Problem(f"example2d_{number}", n, f, u)
+
+
+def initial_guess2(p: Problem, interior: float | np.ndarray = 0.0) -> np.ndarray:
+    u = np.empty_like(p.u_exact)
+    u[...] = interior
+    u[0, :] = p.u_exact[0, :]
+    u[-1, :] = p.u_exact[-1, :]
+    u[:, 0] = p.u_exact[:, 0]
+    u[:, -1] = p.u_exact[:, -1]
+    return u
