@@ -53,7 +53,10 @@ SINGLE = {
 }
 # the standalone Gauss-Seidel solver from 1.01 u to 1e-6 (Table 3 protocol)
 GS = {"gs_example4_33": ("example4", 32, 1e-6)}
-WORKLOADS = sorted(SINGLE) + sorted(GS) + ["batch64", "served"]
+# 2D variant, Section 4 protocol (FMG start, tolerance 1e-6), red-black
+TWO_D = {"ex2d1_8193_fmg": (1, 8192), "ex2d2_8193_fmg": (2, 8192), "ex2d3_8193_fmg": (3, 8192),
+         "ex2d1_1025_fmg": (1, 1024)}
+WORKLOADS = sorted(SINGLE) + sorted(GS) + sorted(TWO_D) + ["batch64", "served"]
 
 
 def parse():
@@ -260,6 +263,46 @@ def run_gs(args, precision):
     return out
 
 
+def run_2d(args, precision):
+    import torch
+
+    from paper_1411_7018_amd import problems as P
+    from paper_1411_7018_amd.solver2d import Solver2D
+
+    ex, n = TWO_D[args.workload]
+    steps = args.steps or 5
+    warmup = 1 if args.warmup is None else args.warmup
+    prob = P.example2d(ex, n)
+    u0 = torch.from_numpy(P.initial_guess2(prob)).cuda()
+    f = torch.from_numpy(prob.f).cuda()
+    u = torch.empty_like(u0)
+    s = Solver2D(n)
+
+    def step():
+        u.copy_(u0)
+        return s.solve(u, f, tol=1e-6)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, reps = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        reps.append(step())
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = base_line(args, steps / elapsed, steps, warmup, elapsed, lat, "fp64")
+    out["config"] = {"workload": f"2D Example {ex} on {n + 1}^2, FMG-FAS start, tolerance 1e-6, "
+                                 f"red-black ordering, half-weighting, V(2,2)",
+                     "n": n, "example": ex}
+    out.update({"cycles": reps[-1]["cycles"], "rel_res": reps[-1]["rel_res"],
+                "max_err_vs_exact": float(np.abs(u.cpu().numpy() - prob.u_exact).max()),
+                "updates_per_s": sum(r["point_updates"] for r in reps) / elapsed})
+    return out
+
+
 def run_batch(args, precision):
     import torch
 
@@ -377,6 +420,8 @@ def main():
         out = run_single(args, precision)
     elif args.workload in GS:
         out = run_gs(args, precision)
+    elif args.workload in TWO_D:
+        out = run_2d(args, precision)
     elif args.workload == "batch64":
         out = run_batch(args, precision)
     else:

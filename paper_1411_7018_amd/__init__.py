@@ -18,6 +18,6 @@ __all__ = ["Solver", "levels", "footprint_bytes", "problems", "solver", "batch",
 def __getattr__(name):
     if name in ("Solver", "levels", "footprint_bytes"):
         return getattr(importlib.import_module(".solver", __name__), name)
-    if name in ("problems", "solver", "batch", "server", "build", "autotune"):
+    if name in ("problems", "solver", "solver2d", "batch", "server", "build", "autotune"):
         return importlib.import_module("." + name, __name__)
     raise AttributeError(name)

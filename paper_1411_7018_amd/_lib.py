@@ -38,6 +38,15 @@ class ma_params(ctypes.Structure):
                 ("max_blocks", ctypes.c_int), ("strip_rows", ctypes.c_int)]
 
 
+class ma2d_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+                ("nu0", ctypes.c_int), ("order", ctypes.c_int), ("restriction", ctypes.c_int),
+                ("max_cycles", ctypes.c_int), ("tol", ctypes.c_double)]
+
+
+MA2D_COLOR4, MA2D_RED_BLACK = 0, 1
+
+
 class ma_report(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("outer", ctypes.c_int), ("init_cycles", ctypes.c_int),
                 ("converged", ctypes.c_int), ("res0", ctypes.c_double), ("res", ctypes.c_double),
@@ -103,6 +112,24 @@ _L.ma_batch_add.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_uint,
 _L.ma_batch_tick.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
 _L.ma_batch_report.argtypes = [_vp, ctypes.c_int, _R]
 _L.ma_batch_remove.argtypes = [_vp, ctypes.c_int]
+_P2 = ctypes.POINTER(ma2d_params)
+_L.ma2d_params_default.argtypes = [_P2, ctypes.c_int]
+_L.ma2d_params_default.restype = None
+_L.ma2d_footprint_bytes.argtypes = [_P2]
+_L.ma2d_footprint_bytes.restype = ctypes.c_size_t
+_L.ma2d_create.argtypes = [_P2, _vp, ctypes.POINTER(_vp)]
+_L.ma2d_destroy.argtypes = [_vp]
+_L.ma2d_destroy.restype = None
+_L.ma2d_last_error.argtypes = [_vp]
+_L.ma2d_last_error.restype = ctypes.c_char_p
+_L.ma2d_sweep.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+_L.ma2d_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
+_L.ma2d_vcycle.argtypes = [_vp, _vp, _vp]
+_L.ma2d_fmg.argtypes = [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_longlong)]
+_L.ma2d_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
+for _name in ("ma2d_create", "ma2d_sweep", "ma2d_residual", "ma2d_vcycle", "ma2d_fmg",
+              "ma2d_solve"):
+    getattr(_L, _name).restype = ctypes.c_int
 for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
               "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
               "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_add",
@@ -115,7 +142,9 @@ EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", 
            "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
            "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
            "ma_batch_last_error", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
-           "ma_batch_remove")
+           "ma_batch_remove", "ma2d_params_default", "ma2d_footprint_bytes", "ma2d_create",
+           "ma2d_destroy", "ma2d_last_error", "ma2d_sweep", "ma2d_residual", "ma2d_vcycle",
+           "ma2d_fmg", "ma2d_solve")
 
 
 def lib() -> ctypes.CDLL:
@@ -263,3 +292,61 @@ def ma_batch_report(b: int, slot: int) -> ma_report:
 
 def ma_batch_remove(b: int, slot: int) -> None:
     _check(_L.ma_batch_remove(b, int(slot)), batch=b)
+
+
+# ---------------------------------------------------------------------------
+# 2D variant (include/ma2d.h)
+# ---------------------------------------------------------------------------
+def _check2(st: int, h=None):
+    if st != MA_OK:
+        raise MAError(st, (_L.ma2d_last_error(h) or b"").decode())
+
+
+def ma2d_params_default(n: int) -> ma2d_params:
+    p = ma2d_params()
+    _L.ma2d_params_default(ctypes.byref(p), int(n))
+    return p
+
+
+def ma2d_footprint_bytes(p: ma2d_params) -> int:
+    return _L.ma2d_footprint_bytes(ctypes.byref(p))
+
+
+def ma2d_create(p: ma2d_params, stream: int | None) -> int:
+    h = _vp()
+    _check2(_L.ma2d_create(ctypes.byref(p), stream or None, ctypes.byref(h)))
+    return h.value
+
+
+def ma2d_destroy(h: int) -> None:
+    _L.ma2d_destroy(h)
+
+
+def ma2d_sweep(h: int, u: int, f: int, count: int) -> int:
+    nc = ctypes.c_longlong()
+    _check2(_L.ma2d_sweep(h, u, f, int(count), ctypes.byref(nc)), h)
+    return nc.value
+
+
+def ma2d_residual(h: int, u: int, f: int, r: int | None) -> float:
+    out = ctypes.c_double()
+    _check2(_L.ma2d_residual(h, u, f, r or None, ctypes.byref(out)), h)
+    return out.value
+
+
+def ma2d_vcycle(h: int, u: int, f: int) -> None:
+    _check2(_L.ma2d_vcycle(h, u, f), h)
+
+
+def ma2d_fmg(h: int, u: int, f: int) -> int:
+    nc = ctypes.c_longlong()
+    _check2(_L.ma2d_fmg(h, u, f, ctypes.byref(nc)), h)
+    return nc.value
+
+
+def ma2d_solve(h: int, u: int, f: int, tol: float, flags: int) -> ma_report:
+    rep = ma_report()
+    st = _L.ma2d_solve(h, u, f, float(tol), int(flags), ctypes.byref(rep))
+    if st != MA_OK:
+        raise MAError(st, (_L.ma2d_last_error(h) or b"").decode(), rep.as_dict())
+    return rep

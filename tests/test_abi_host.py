@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI that need no GPU: the library loads, every
-symbol declared in include/ma.h is exported, and the pure host entry points
+symbol declared in include/ma.h and include/ma2d.h is exported, and the pure host entry points
 (defaults, level hierarchy, footprint, argument validation) behave."""
 import ctypes
 import os
@@ -11,9 +11,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "ma.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ma_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in ("ma.h", "ma2d.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(ma2?d?_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_the_abi():
@@ -85,3 +88,17 @@ def test_null_handles_are_rejected():
     lib.ma_destroy(None)
     out = ctypes.c_void_p()
     assert lib.ma_batch_create(0, None, ctypes.byref(out)) == L.MA_ERR_ARG
+
+
+def test_2d_params_and_footprint():
+    from paper_1411_7018_amd import _lib as L
+    p = L.ma2d_params_default(256)
+    assert (p.n, p.nu1, p.nu2, p.nu0) == (256, 2, 2, 1)
+    assert p.order == L.MA2D_RED_BLACK and p.restriction == L.MA_RESTRICT_HALF
+    assert p.tol == 1e-6
+    fp = L.ma2d_footprint_bytes(p)
+    assert 257 ** 2 * 8 * 2 < fp < 257 ** 2 * 8 * 4
+    p.order = 7
+    assert L.ma2d_footprint_bytes(p) == 0
+    with pytest.raises(L.MAError):
+        L.ma2d_create(p, None)
