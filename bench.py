@@ -73,7 +73,7 @@ def parse():
                          "(one FMG-FAS iteration as the first cycle); default per workload")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--tuned", default=None,
-                    help="coarse_n,max_blocks[,strip_rows] to use instead of running the "
+                    help="coarse_n,max_blocks[,strip_rows[,block_n]] to use instead of running the "
                          "autotuner")
     ap.add_argument("--copy-calibration", type=float, default=None, metavar="MB",
                     help="only run 20 plain device copies of MB megabytes (counter "
@@ -142,10 +142,10 @@ def pick_tuning(args, solvers, us, fs, ticks):
 
     if args.tuned:
         vals = [int(v) for v in args.tuned.split(",")]
-        cn, mb, sr = (vals + [0])[:3]
+        cn, mb, sr, bn = (vals + [0, 0])[:4]
         for s in solvers:
-            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
-        return autotune.Choice(cn, mb, sr, float("nan"), [])
+            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn)
+        return autotune.Choice(cn, mb, sr, bn, float("nan"), [])
     if args.no_tune:
         return None
     return autotune.tune(solvers, us, fs, ticks=ticks)
@@ -170,7 +170,8 @@ def tune_note(choice):
     if choice is None:
         return None
     return {"coarse_n": choice.coarse_n, "max_blocks": choice.max_blocks,
-            "strip_rows": choice.strip_rows, "ms_per_tick": 1e3 * choice.seconds_per_tick}
+            "strip_rows": choice.strip_rows, "block_n": choice.block_n,
+            "ms_per_tick": 1e3 * choice.seconds_per_tick}
 
 
 def run_single(args, precision):

@@ -55,11 +55,19 @@ typedef enum { MA_COLOR4 = 0, MA_COLOR8 = 1 } ma_order;
  * weighting (27 points, tensor product of 1/4, 1/2, 1/4) is the default. */
 typedef enum { MA_RESTRICT_FULL = 0, MA_RESTRICT_HALF = 1 } ma_restriction;
 
-/* Smoother kernel selection (same arithmetic, different data movement). */
+/* Smoother kernel selection.  Every choice computes bitwise the same sweep
+ * (the same pointwise update on the same neighbour values); they differ in
+ * data movement.  The block sweep runs the four colour phases of one sweep
+ * in one launch: each workgroup updates a block of the grid with a halo in
+ * LDS, recomputing the halo's updates, out of place into a second array
+ * (pairs of sweeps go u -> t -> u; an odd last sweep runs per colour).  It
+ * applies to the 4-colour ordering in MA_FP64 only. */
 typedef enum {
-    MA_SMOOTHER_AUTO = 0,      /* fused where available, else per colour        */
+    MA_SMOOTHER_AUTO = 0,      /* block sweeps on levels with n <= block_n that
+                                  have more than coarse_n intervals, one
+                                  launch per colour phase elsewhere           */
     MA_SMOOTHER_COLOR = 1,     /* one in-place launch per colour phase          */
-    MA_SMOOTHER_FUSED = 2      /* all colour phases of a sweep in one launch     */
+    MA_SMOOTHER_FUSED = 2      /* block sweeps on every level                    */
 } ma_smoother;
 
 /* ma_solve flag: replace the interior of u by the initial guess that solves
@@ -87,8 +95,11 @@ typedef struct {
     int init_max_cycles;   /* cap on the linear V-cycles of MA_INIT_POISSON      */
     int inner_cycles;      /* MA_MIXED: FP32 V-cycles per outer correction       */
     int profile;           /* 1: time finest-level smoothing with HIP events     */
-    int tile_config;       /* fused sweep tile shape: 0 automatic, 1..6 fixed    */
-    int zchunk;            /* fused sweep planes per z-chunk: 0 automatic        */
+    int tile_config;       /* block sweep shape: 0 automatic, 1..5 fixed (8^3
+                              blocks of 256, 512, 1024 threads; 16x8x4 of 256;
+                              16x16x8 of 512)                                    */
+    int block_n;           /* MA_SMOOTHER_AUTO: block sweeps on levels with
+                              n <= block_n; 0 automatic (64), -1 never          */
     int graphs;            /* 1: replay each cycle from a captured hipGraph      */
     int coarse_n;          /* levels with n <= coarse_n (0..32) run inside one
                               single-workgroup kernel per solve; 0: off         */
@@ -154,10 +165,11 @@ const char *ma_last_error(const ma_solver *s);
 ma_status ma_set_stream(ma_solver *s, void *hip_stream);
 
 /* Change the launch shape of later cycles without touching the hierarchy:
- * coarse_n, max_blocks and strip_rows as in ma_params (the autotuner's
- * knobs).  The arithmetic, and so every result, is the same for every value.
- * Errors: MA_ERR_ARG for values outside their ranges (nothing changes). */
-ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows);
+ * coarse_n, max_blocks, strip_rows and block_n as in ma_params (the
+ * autotuner's knobs).  The arithmetic, and so every result, is the same for
+ * every value.  Errors: MA_ERR_ARG for values outside their ranges (nothing
+ * changes). */
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows, int block_n);
 
 /* Solve det(D^2 u) = f (Algorithm 1 repeated under the stopping rule of
  * Section 4): run V(nu1,nu2) cycles until the discrete L2 residual is

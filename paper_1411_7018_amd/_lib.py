@@ -33,7 +33,7 @@ class ma_params(ctypes.Structure):
                 ("max_cycles", ctypes.c_int), ("tol", ctypes.c_double),
                 ("init_tol", ctypes.c_double), ("init_max_cycles", ctypes.c_int),
                 ("inner_cycles", ctypes.c_int), ("profile", ctypes.c_int),
-                ("tile_config", ctypes.c_int), ("zchunk", ctypes.c_int),
+                ("tile_config", ctypes.c_int), ("block_n", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("coarse_n", ctypes.c_int),
                 ("max_blocks", ctypes.c_int), ("strip_rows", ctypes.c_int)]
 
@@ -90,7 +90,7 @@ _L.ma_destroy.restype = None
 _L.ma_last_error.argtypes = [_vp]
 _L.ma_last_error.restype = ctypes.c_char_p
 _L.ma_set_stream.argtypes = [_vp, _vp]
-_L.ma_retune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_L.ma_retune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _L.ma_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_vcycle.argtypes = [_vp, _vp, _vp]
 _L.ma_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
@@ -194,8 +194,8 @@ def ma_set_stream(h: int, stream: int | None) -> None:
     _check(_L.ma_set_stream(h, stream or None), h)
 
 
-def ma_retune(h: int, coarse_n: int, max_blocks: int, strip_rows: int) -> None:
-    _check(_L.ma_retune(h, int(coarse_n), int(max_blocks), int(strip_rows)), h)
+def ma_retune(h: int, coarse_n: int, max_blocks: int, strip_rows: int, block_n: int = 0) -> None:
+    _check(_L.ma_retune(h, int(coarse_n), int(max_blocks), int(strip_rows), int(block_n)), h)
 
 
 def ma_solve(h: int, u: int, f: int, tol: float, flags: int) -> ma_report:

@@ -10,6 +10,9 @@ cut into launches:
     single-workgroup coarse-level kernel instead of one launch per phase.
   * ``strip_rows`` -- the width of the y-strips in which a launch walks its
     rows along z: narrow strips keep the planes a stencil re-reads in L2.
+  * ``block_n``    -- levels with n <= block_n (above coarse_n) smooth with
+    block sweeps (the four colour phases of a sweep in one launch) instead
+    of one launch per colour phase; -1 turns them off.
 
 ``tune`` times the candidates on the device, on the caller's own
 solvers and data (a copy of u), with one tick per candidate for graph
@@ -30,6 +33,7 @@ import torch
 BLOCKS = (4096, 8192, 16384, 32768, 65536)
 COARSE = (0, 8, 16, 32)
 STRIPS = (8, 32, 128, 4096)
+BLOCK_N = (-1, 32, 64, 128)
 
 
 @dataclasses.dataclass
@@ -37,12 +41,14 @@ class Choice:
     coarse_n: int
     max_blocks: int
     strip_rows: int
+    block_n: int
     seconds_per_tick: float
-    table: list          # [(coarse_n, max_blocks, strip_rows, seconds_per_tick), ...]
+    table: list  # [(coarse_n, max_blocks, strip_rows, block_n, seconds_per_tick), ...]
 
     def as_dict(self) -> dict:
         return {"coarse_n": self.coarse_n, "max_blocks": self.max_blocks,
-                "strip_rows": self.strip_rows, "seconds_per_tick": self.seconds_per_tick,
+                "strip_rows": self.strip_rows, "block_n": self.block_n,
+                "seconds_per_tick": self.seconds_per_tick,
                 "table": [list(r) for r in self.table]}
 
 
@@ -72,12 +78,13 @@ def _time_ticks(solvers, us, fs, ticks: int) -> float:
 
 
 def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE, strips=STRIPS,
-         verbose: bool = False) -> Choice:
+         block_ns=BLOCK_N, verbose: bool = False) -> Choice:
     """Pick the launch shape of one batched tick of these solves and retune
     the solvers to it.  The knobs barely interact (coarse_n moves work
     between the coarse-level kernel and the row kernels; max_blocks and
-    strip_rows shape the row kernels), so they are searched one after the
-    other -- coarse_n x max_blocks on the default strips, then strip_rows --
+    strip_rows shape the row kernels; block_n moves mid-level sweeps to the
+    block kernel), so they are searched one after the other -- coarse_n x
+    max_blocks on the default strips, then strip_rows, then block_n --
     instead of over the full product.  The solves must fit one batch (at
     most 64, shared smoothing parameters)."""
     if not solvers:
@@ -92,26 +99,32 @@ def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE, strips=S
         starts.append(w)
     table = []
 
-    def trial(cn, mb, sr):
+    def trial(cn, mb, sr, bn):
         for s in solvers:
-            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
+            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn)
         t = min(_time_ticks(solvers, starts, fs, ticks) for _ in range(2))
-        table.append((cn, mb, sr, t))
+        table.append((cn, mb, sr, bn, t))
         if verbose:
-            print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d} strip_rows={sr:4d}: "
-                  f"{1e3 * t:.3f} ms/tick", flush=True)
+            print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d} strip_rows={sr:4d} "
+                  f"block_n={bn:4d}: {1e3 * t:.3f} ms/tick", flush=True)
         return t
+
+    def best():
+        return min(table, key=lambda r: r[4])
 
     for cn in coarse:
         for mb in blocks:
-            trial(cn, mb, 0)
-    cn, mb, _, _ = min(table, key=lambda r: r[3])
+            trial(cn, mb, 0, 0)
+    cn, mb, _, _, _ = best()
     for sr in strips:
-        trial(cn, mb, sr)
-    cn, mb, sr, t = min(table, key=lambda r: r[3])
+        trial(cn, mb, sr, 0)
+    cn, mb, sr, _, _ = best()
+    for bn in block_ns:
+        trial(cn, mb, sr, bn)
+    cn, mb, sr, bn, t = best()
     for s in solvers:
-        s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr)
-    return Choice(cn, mb, sr, t, table)
+        s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn)
+    return Choice(cn, mb, sr, bn, t, table)
 
 
 def load(path: str, k: str) -> dict | None:

@@ -8,6 +8,17 @@
 
 namespace mafas {
 
+// A pointer read from a device-side table is generic to the compiler, which
+// then accesses it with FLAT instructions; those count against the LDS wait
+// counter too, so waiting for an LDS access would also wait for every
+// global load in flight.  Casting to the global address space gives
+// global_load / global_store instead.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *to_global(T *p)
+{
+    return (__attribute__((address_space(1))) T *)(p);
+}
+
 struct Hess {
     double xx, yy, zz, xy, xz, yz;
 };

@@ -10,6 +10,7 @@
 // is a batch of one.
 #pragma once
 
+#include "ma_fsweep.h"
 #include "ma_runtime.h"
 
 #include <vector>
@@ -97,6 +98,11 @@ hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color
                           unsigned long long *nfall);
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, const double *partials,
                                  double *out);
+// block sweeps of an FsList (ma_fsweep.h): cfg block shape, blocks >= tiles
+hipError_t launch_bsweep(hipStream_t st, int op, int cfg, const FsList *L, int blocks,
+                         unsigned long long *nonconvex);
+void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *F, int op,
+                 int slot, FsGrid *G);
 // one workgroup per TailList entry (blocks >= entries); mode: Engine::Mode
 hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const TailList *T,
                        int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount,
@@ -119,8 +125,8 @@ class Engine {
 
     // Define the solves (at most kMaxGrids) and the stream the caller orders
     // its work on.  All solvers must share nu1, nu2, nu0, order, restriction,
-    // precision, inner_cycles, coarse_n, max_blocks and strip_rows.  graphs: replay
-    // ticks from captured hipGraphs.
+    // precision, inner_cycles, coarse_n, max_blocks, strip_rows, smoother,
+    // tile_config and block_n.  graphs: replay ticks from captured hipGraphs.
     ma_status set(const std::vector<SolveRef> &solves, hipStream_t user, bool graphs,
                   bool profile);
     // One V-cycle (MA, LAP) or one outer correction (MIXED) of every active
@@ -166,13 +172,15 @@ class Engine {
     std::vector<SolveRef> solves_;
     hipStream_t user_ = nullptr, stream_ = nullptr;
     hipEvent_t ev_in_ = nullptr;
-    bool graphs_ = true, profile_ = false, fused_ = false;
+    bool graphs_ = true, profile_ = false;
     std::string err_;
     int D_ = 0;      // multi-block depth of the active solves
     int Dall_ = 0;   // full depth of the active solves
     int nu1_ = 2, nu2_ = 2, nu0_ = 1, order_ = 0, rmode_ = 0, inner_ = 2;
     int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks, strip_rows_ = 0;
+    int smoother_ = MA_SMOOTHER_AUTO, tile_config_ = 0, block_n_ = 0;
     int strip_width(int gy) const;
+    bool block_level(int n) const;     // sweeps of a multi-block n grid as block sweeps
 
     std::vector<char> hbuf_;               // host copy of the lists and the tail table
     std::vector<size_t> loff_;             // byte offset of each list
@@ -187,6 +195,14 @@ class Engine {
     bool mixed_ = false;
 
     std::vector<std::vector<int>> swd_, swu_;  // [depth][sweep] list indices
+    // Block sweeps: [depth][sweep] index of the first of two FsLists (u -> t,
+    // t -> u) running sweeps 2q and 2q + 1 together, or -1 (colour phases);
+    // entries at odd sweeps are unused.
+    std::vector<std::vector<int>> bsd_, bsu_;
+    std::vector<size_t> fsoff_;            // byte offset of each FsList
+    std::vector<int> fsblocks_;            // blocks per FsList launch (0: no grid)
+    std::vector<int> fscfg_;               // block shape per FsList
+    size_t fs_stride_ = 0;
     std::vector<int> res_, rst_, pro_, inj_;
     int norm_ = -1, accum_ = -1, zero_ = -1;
 

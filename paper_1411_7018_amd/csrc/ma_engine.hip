@@ -700,26 +700,19 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         else if (p.nu1 != p0->nu1 || p.nu2 != p0->nu2 || p.nu0 != p0->nu0 || p.order != p0->order ||
                  p.restriction != p0->restriction || p.precision != p0->precision ||
                  p.inner_cycles != p0->inner_cycles || p.coarse_n != p0->coarse_n ||
-                 p.max_blocks != p0->max_blocks || p.strip_rows != p0->strip_rows)
+                 p.max_blocks != p0->max_blocks || p.strip_rows != p0->strip_rows ||
+                 p.smoother != p0->smoother || p.tile_config != p0->tile_config ||
+                 p.block_n != p0->block_n)
             return fail(MA_ERR_ARG,
                         "solvers in one batch must share smoothing counts, ordering, "
-                        "restriction, precision, inner cycles, coarse_n, max_blocks and "
-                        "strip_rows");
+                        "restriction, precision, inner cycles, coarse_n, max_blocks, "
+                        "strip_rows, smoother, tile_config and block_n");
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
     // A captured tick reads the grids' operand pointers from the device
-    // tables, which every rebuild rewrites; what it holds as plain kernel
-    // arguments is the partials buffer and, on the fused path, the grids
-    // themselves.  A change of either invalidates the graphs.
-    const bool fused = solves.size() == 1 && p0->smoother == MA_SMOOTHER_FUSED &&
-                       p0->order == MA_COLOR4;
-    bool same = solves.size() == solves_.size();
-    for (size_t i = 0; same && i < solves.size(); ++i)
-        same = solves[i].s == solves_[i].s && solves[i].u == solves_[i].u &&
-               solves[i].f == solves_[i].f;
-    if (fused != fused_ || (fused && !same))
-        drop_graphs();
+    // tables, which every rebuild rewrites; what it holds as a plain kernel
+    // argument is the partials buffer, whose reallocation drops the graphs.
     solves_ = solves;
     user_ = user;
     graphs_ = graphs;
@@ -734,7 +727,9 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     coarse_n_ = p0->coarse_n;
     max_blocks_ = p0->max_blocks > 0 ? p0->max_blocks : kDefaultMaxBlocks;
     strip_rows_ = p0->strip_rows;
-    fused_ = fused;
+    smoother_ = p0->smoother;
+    tile_config_ = p0->tile_config;
+    block_n_ = p0->block_n;
     built_ = false;
     if (!stream_) {
         E_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
@@ -797,6 +792,18 @@ int Engine::strip_width(int gy) const
 {
     const int w = strip_rows_ > 0 ? strip_rows_ : 32;
     return std::max(1, std::min(w, gy));
+}
+
+// Block sweeps for a multi-block level of n intervals (4-colour FP64 only;
+// the caller excludes MODE_MIXED).
+bool Engine::block_level(int n) const
+{
+    if (order_ != MA_COLOR4 || smoother_ == MA_SMOOTHER_COLOR)
+        return false;
+    if (smoother_ == MA_SMOOTHER_FUSED)
+        return true;
+    const int lim = block_n_ == 0 ? 64 : block_n_;
+    return n <= lim;
 }
 
 int Engine::multiblock_levels(int i) const
@@ -1051,6 +1058,83 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         tail_blocks_ = bound;
     }
 
+    // Block-sweep lists, after the tail table.  Sweeps 2q and 2q + 1 of a
+    // depth run as a block sweep u -> t followed by t -> u when the depth's
+    // grids take block sweeps and every solve with that level takes part in
+    // both sweeps.  Both decisions cover all solves of the engine, active or
+    // not, so they do not change when solves pause or finish.
+    fsoff_.clear();
+    fsblocks_.clear();
+    fscfg_.clear();
+    fs_stride_ = fs_list_bytes(S);
+    bsd_.assign(D_, std::vector<int>());
+    bsu_.assign(D_, std::vector<int>());
+    {
+        const int op = mode == MODE_LAP ? OP_LAP : OP_MA;
+        for (int d = 0; d < D_; ++d) {
+            bool blk = !mixed;
+            int nmax = 0;
+            for (int i = 0; i < S && blk; ++i) {
+                if (!solves_[i].s || multiblock_levels(i) <= d)
+                    continue;
+                const int n = solves_[i].s->lv[d].n;
+                blk = block_level(n);
+                nmax = std::max(nmax, n);
+            }
+            const int cfg = tile_config_ > 0 ? tile_config_ - 1 : bsweep_pick(nmax);
+            auto has = [&](int i) { return solves_[i].s && multiblock_levels(i) > d; };
+            auto pairs = [&](int nsw, auto count, std::vector<int> &out) {
+                out.assign(nsw, -1);
+                if (!blk)
+                    return;
+                for (int k = 0; k + 1 < nsw; k += 2) {
+                    bool same = true;
+                    for (int i = 0; i < S && same; ++i)
+                        if (has(i))
+                            same = (count(i) > k) == (count(i) > k + 1);
+                    if (!same)
+                        continue;
+                    out[k] = int(fsoff_.size());
+                    for (int half = 0; half < 2; ++half) {
+                        FsList L;
+                        L.ngrids = 0;
+                        L.pad[0] = L.pad[1] = 0;
+                        int start = 0;
+                        long bound = 0;
+                        for (int i = 0; i < S; ++i) {
+                            if (!has(i) || count(i) <= k)
+                                continue;
+                            const ma_solver *sv = solves_[i].s;
+                            double *u = const_cast<double *>(level_u(i, d, mode));
+                            double *t = sv->lv[d].t;
+                            FsGrid G;
+                            bsweep_grid(cfg, sv->lv[d].n, half ? t : u, half ? u : t,
+                                        level_F(i, d, mode), op, i, &G);
+                            const int tiles = G.tiles_x * G.tiles_y * G.tiles_z;
+                            bound += tiles;
+                            if (!active[i])
+                                continue;
+                            G.start = start;
+                            start += tiles;
+                            L.g[L.ngrids++] = G;
+                        }
+                        L.total = start;
+                        const size_t off = hbuf_.size();
+                        fsoff_.push_back(off);
+                        fsblocks_.push_back(int(bound));
+                        fscfg_.push_back(cfg);
+                        hbuf_.resize(off + fs_stride_, 0);
+                        std::memcpy(hbuf_.data() + off, &L, fs_list_bytes(L.ngrids));
+                    }
+                }
+            };
+            pairs(int(swd_[d].size()),
+                  [&](int i) { return d < levels(i) - 1 ? nu1_ : nu0_; }, bsd_[d]);
+            pairs(int(swu_[d].size()), [&](int i) { return d < levels(i) - 1 ? nu2_ : 0; },
+                  bsu_[d]);
+        }
+    }
+
     prof_bytes_tick_ = 0.0;
     prof_launches_tick_ = 0;
     for (int i = 0; i < S; ++i)
@@ -1065,10 +1149,20 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         const int reps = mixed ? inner_ : 1;
         const int colours = order_ == 1 ? 8 : 4;
         int launches = 0;
-        for (int idx : swd_[0])
-            launches += lgrid_[idx] > 0 ? colours : 0;
-        for (int idx : swu_[0])
-            launches += lgrid_[idx] > 0 ? colours : 0;
+        auto count = [&](const std::vector<int> &lists, const std::vector<int> &pairs) {
+            for (size_t k = 0; k < lists.size();) {
+                if (k + 1 < lists.size() && pairs[k] >= 0) {
+                    launches += (fsblocks_[pairs[k]] > 0 ? 1 : 0) +
+                                (fsblocks_[pairs[k] + 1] > 0 ? 1 : 0);
+                    k += 2;
+                } else {
+                    launches += lgrid_[lists[k]] > 0 ? colours : 0;
+                    ++k;
+                }
+            }
+        };
+        count(swd_[0], bsd_[0]);
+        count(swu_[0], bsu_[0]);
         prof_launches_tick_ = reps * launches;
     }
     built_mode_ = mode;
@@ -1138,43 +1232,31 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
         return MA_OK;
     };
     const int SW = mixed ? LK_MSWEEP : LK_SWEEP;
-    // the explicitly selected fused smoother of a one-solve FP64 engine:
-    // sweeps of depth d in out-of-place pairs, a leftover sweep per colour
-    auto sweeps = [&](const std::vector<int> &lists, int d) -> ma_status {
-        const ma_solver *s0 = solves_[0].s;
-        const int nd = s0->lv[d].n;
-        if (fused_ && !mixed && nd >= 4) {
-            double *u = const_cast<double *>(level_u(0, d, mode));
-            const double *F = level_F(0, d, mode);
-            double *t = s0->lv[d].t;
-            size_t cnt = 0;
-            for (int idx : lists)
-                cnt += lng_[idx] > 0 ? 1 : 0;
-            size_t done = 0;
-            if (cnt >= 2) {
-                E_HIP(launch_copy_boundary(stream_, nd, u, t));
-                for (; done + 2 <= cnt; done += 2) {
-                    E_HIP(launch_sweep_fused(stream_, op, nd, u, t, F, dcount_, s0->p.tile_config - 1,
-                                             s0->p.zchunk));
-                    E_HIP(launch_sweep_fused(stream_, op, nd, t, u, F, dcount_, s0->p.tile_config - 1,
-                                             s0->p.zchunk));
+    auto FL = [&](int f) { return reinterpret_cast<const FsList *>(dl_ + fsoff_[f]); };
+    // the sweeps of one depth: paired sweeps as two block sweeps, the others
+    // one launch per colour phase
+    auto sweeps = [&](const std::vector<int> &lists, const std::vector<int> &pairs) -> ma_status {
+        for (size_t k = 0; k < lists.size();) {
+            if (k + 1 < lists.size() && pairs[k] >= 0) {
+                for (int h = 0; h < 2; ++h) {
+                    const int f = pairs[k] + h;
+                    if (fsblocks_[f] > 0)
+                        E_HIP(launch_bsweep(stream_, op, fscfg_[f], FL(f), fsblocks_[f], dcount_));
                 }
-            }
-            for (size_t q = done; q < lists.size(); ++q)
+                k += 2;
+            } else {
                 for (int c = 0; c < colours; ++c)
-                    MA_TRY(go(SW, lists[q], c));
-            return MA_OK;
+                    MA_TRY(go(SW, lists[k], c));
+                ++k;
+            }
         }
-        for (int idx : lists)
-            for (int c = 0; c < colours; ++c)
-                MA_TRY(go(SW, idx, c));
         return MA_OK;
     };
     auto vcycle = [&]() -> ma_status {
         for (int d = 0; d < D_; ++d) {
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
-            MA_TRY(sweeps(swd_[d], d));
+            MA_TRY(sweeps(swd_[d], bsd_[d]));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
             MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
@@ -1188,7 +1270,7 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
             MA_TRY(go(mixed ? LK_MPROLONG : LK_PROLONG, pro_[d], 0));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
-            MA_TRY(sweeps(swu_[d], d));
+            MA_TRY(sweeps(swu_[d], bsu_[d]));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
         }
@@ -1224,6 +1306,11 @@ std::vector<int> Engine::shape() const
     s.push_back(strip_rows_);
     s.push_back(int(loff_.size()));
     s.insert(s.end(), lgrid_.begin(), lgrid_.end());
+    s.push_back(int(fsoff_.size()));
+    s.push_back(fsoff_.empty() ? 0 : int(fsoff_[0]));
+    s.push_back(int(fs_stride_));
+    s.insert(s.end(), fsblocks_.begin(), fsblocks_.end());
+    s.insert(s.end(), fscfg_.begin(), fscfg_.end());
     return s;
 }
 

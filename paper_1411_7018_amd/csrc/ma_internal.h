@@ -24,15 +24,14 @@ size_t residual_partials(int n);
 hipError_t launch_sweep_color(hipStream_t st, int op, int order, int n, double *u,
                               const double *F, unsigned long long *nonconvex);
 
-// One sweep, all four colour phases in a single launch reading u_in and
-// writing u_out (z-streamed, LDS-tiled; 4-colour ordering only).  u_out must
-// hold the same Dirichlet layer as u_in.
-// cfg: tile shape index (< 0: automatic), zc: planes per z-chunk (< 1: auto).
-hipError_t launch_sweep_fused(hipStream_t st, int op, int n, const double *u_in, double *u_out,
-                              const double *F, unsigned long long *nonconvex, int cfg, int zc);
-bool fused_supported(int n);
-int fused_num_configs();
-void fused_pick(int n, int *cfg, int *zc);
+// The block sweep (ma_fsweep.h): one sweep, all four colour phases in a
+// single launch reading u_in and writing u_out (4-colour ordering only);
+// u_out receives the Dirichlet layer too.  cfg: block shape index (< 0:
+// automatic for n).  Bitwise equal to launch_sweep_color.
+hipError_t launch_bsweep_one(hipStream_t st, int op, int cfg, int n, const double *u_in,
+                             double *u_out, const double *F, unsigned long long *nonconvex);
+int bsweep_num_configs();
+int bsweep_pick(int n);
 
 // --- residual and norm ----------------------------------------------------
 // r = F - S(u) (interior; 0 on the boundary; r may be null) and per-block sums

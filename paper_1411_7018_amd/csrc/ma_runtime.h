@@ -32,7 +32,7 @@ struct Level {
     double *b = nullptr;   // right-hand side (coarse levels)
     double *w = nullptr;   // injected fine approximation (coarse levels)
     double *r = nullptr;   // residual
-    double *t = nullptr;   // out-of-place target of the fused sweep
+    double *t = nullptr;   // out-of-place target of the block sweep
 };
 
 // FP32 inner hierarchy of the mixed-precision form (one per level).
@@ -46,6 +46,8 @@ struct MixedLevel {
 };
 
 size_t hierarchy_bytes(const ma_params *p);
+// Largest n whose sweeps MA_SMOOTHER_AUTO runs as block sweeps (-1: none).
+inline int block_limit(const ma_params &p) { return p.block_n == 0 ? 64 : p.block_n; }
 size_t mixed_bytes(const ma_params *p);
 
 hipError_t launch_fill(hipStream_t st, size_t count, double v, double *dst);
@@ -80,7 +82,7 @@ struct ma_solver {
     ma_status fail(ma_status st, const std::string &msg);
     ma_status alloc(double **q, size_t count);
     ma_status allocate();
-    bool use_fused(int l) const;
+    bool use_block(int l) const;
     int rmode() const;
     // single-grid kernels behind the component entry points
     ma_status smooth(int l, double *u, const double *F, int count, int op);

@@ -50,8 +50,9 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "unknown smoother";
         return false;
     }
-    if (p->tile_config < 0 || p->tile_config > fused_num_configs() || p->zchunk < 0) {
-        why = "tile_config must be in 0..6 and zchunk >= 0";
+    if (p->tile_config < 0 || p->tile_config > bsweep_num_configs() || p->block_n < -1 ||
+        p->block_n > 2048) {
+        why = "tile_config must be in 0..5 and block_n in -1..2048";
         return false;
     }
     if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1 ||
@@ -92,7 +93,7 @@ double mafas::now_seconds()
 
 // ---------------------------------------------------------------------------
 // Hierarchy layout (FP64, (n_l+1)^3 each):
-//   level 0: r (residual), R (Poisson right-hand side), t (fused target);
+//   level 0: r (residual), R (Poisson right-hand side), t (block-sweep target);
 //   level l >= 1: u, b, w, r, t.
 // Plus the single-grid norm partials, the batch-of-one engine's partials and
 // lists, and the MA_MIXED FP32 hierarchy.
@@ -198,7 +199,7 @@ ma_status ma_set_stream(ma_solver *s, void *hip_stream)
     return MA_OK;
 }
 
-ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows)
+ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows, int block_n)
 {
     if (!s)
         return MA_ERR_ARG;
@@ -206,6 +207,7 @@ ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows)
     q.coarse_n = coarse_n;
     q.max_blocks = max_blocks;
     q.strip_rows = strip_rows;
+    q.block_n = block_n;
     std::string why;
     if (!valid_params(&q, why))
         return s->fail(MA_ERR_ARG, why);
@@ -517,13 +519,17 @@ ma_status ma_solver::allocate()
     return MA_OK;
 }
 
-bool ma_solver::use_fused(int l) const
+// Block sweeps (4-colour FP64 sweeps of level l in one launch each): every
+// level with MA_SMOOTHER_FUSED, levels with coarse_n < n <= block_n with
+// MA_SMOOTHER_AUTO.
+bool ma_solver::use_block(int l) const
 {
     if (p.order != MA_COLOR4 || p.smoother == MA_SMOOTHER_COLOR)
         return false;
     if (p.smoother == MA_SMOOTHER_FUSED)
-        return lv[l].n >= 4;
-    return fused_supported(lv[l].n);
+        return true;
+    const int n = lv[l].n;
+    return n <= block_limit(p) && n > p.coarse_n;
 }
 
 int ma_solver::rmode() const { return p.restriction == MA_RESTRICT_HALF ? 1 : 0; }
@@ -533,14 +539,11 @@ ma_status ma_solver::smooth(int l, double *u, const double *F, int count, int op
 {
     const int n = lv[l].n;
     int done = 0;
-    if (use_fused(l) && count >= 2) {
+    if (use_block(l) && count >= 2) {
         double *t = lv[l].t;
-        MA_HIP(this, launch_copy_boundary(stream, n, u, t));
         for (; done + 2 <= count; done += 2) {
-            MA_HIP(this, launch_sweep_fused(stream, op, n, u, t, F, dcount, p.tile_config - 1,
-                                            p.zchunk));
-            MA_HIP(this, launch_sweep_fused(stream, op, n, t, u, F, dcount, p.tile_config - 1,
-                                            p.zchunk));
+            MA_HIP(this, launch_bsweep_one(stream, op, p.tile_config - 1, n, u, t, F, dcount));
+            MA_HIP(this, launch_bsweep_one(stream, op, p.tile_config - 1, n, t, u, F, dcount));
         }
     }
     for (; done < count; ++done)
