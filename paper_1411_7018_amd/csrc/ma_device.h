@@ -18,6 +18,12 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *to_global(T *p)
 {
     return (__attribute__((address_space(1))) T *)(p);
 }
+// An untyped table entry as a global pointer to T.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(void *p)
+{
+    return (__attribute__((address_space(1))) T *)(p);
+}
 
 struct Hess {
     double xx, yy, zz, xy, xz, yz;

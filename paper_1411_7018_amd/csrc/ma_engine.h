@@ -21,6 +21,8 @@ constexpr int kMaxGrids = 64;          // grids (solve, level) per batched launc
 constexpr int kDefaultMaxBlocks = 16384;
 constexpr int kTailThreads = 512;      // threads of the coarse-level kernel
 constexpr int kMaxTail = 6;            // levels per solve inside that kernel
+constexpr int kTailLdsThreads = 1024;  // threads of its LDS form
+constexpr int kTailLdsDoubles = 18432; // LDS of that form (144 KiB): levels 16, 8, 4, 2
 
 // One grid of one solve inside a batched launch.  Every work item is one
 // wavefront handling 64 nodes of one x-row (bx, by, bz) of a gx x gy x gz
@@ -62,9 +64,17 @@ constexpr size_t list_bytes(int ngrids) { return 16 + sizeof(GridItem) * size_t(
 struct TailLevel {
     GridItem sw, res, rst, pro;
 };
+// LDS form: offsets (in doubles) of each level's u, b, w, r in LDS, -1
+// where the level has no such array (w above the first level, r on the
+// coarsest).
+struct TailLds {
+    int u[kMaxTail], b[kMaxTail], w[kMaxTail], r[kMaxTail];
+};
 struct TailEntry {
     int nlev;
-    int pad[3];
+    int lds;        // 1: the levels fit kTailLdsDoubles
+    int pad[2];
+    TailLds L;
     TailLevel lv[kMaxTail];
 };
 struct TailList {
@@ -107,6 +117,9 @@ void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *
 hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const TailList *T,
                        int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount,
                        unsigned long long *nfall);
+// the LDS form (MODE_MA, MODE_LAP; every entry with lds = 1)
+hipError_t launch_tail_lds(hipStream_t st, int mode, int order, int rmode, const TailList *T,
+                           int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount);
 
 struct SolveRef {
     ma_solver *s = nullptr;
@@ -188,6 +201,7 @@ class Engine {
     std::vector<int> lgrid_;               // blocks per list launch (0: never any grid)
     size_t toff_ = 0;                      // byte offset of the tail table
     int tail_blocks_ = 0;                  // blocks of the tail launch (0: no tail)
+    bool tail_lds_ = false;                // the tail launch is the LDS form
     char *dl_ = nullptr;                   // device lists
     size_t dl_cap_ = 0;
     char *hstage_ = nullptr;               // pinned staging for uploads

@@ -34,51 +34,49 @@ __device__ __forceinline__ double wave_sum64(double v)
 }
 
 // ---------------------------------------------------------------------------
-// Per-node phases.  p is the node's linear index, (sy, sz) the strides of
-// G's grid.
+// Per-node phases, written once over pointer types (global memory for the
+// row kernels, LDS for the coarse-level kernel), so a node's result is
+// bitwise the same whichever kernel computes it.  p is the node's linear
+// index, (sy, sz) the strides of its grid.
 // ---------------------------------------------------------------------------
-template <int OP>
-__device__ __forceinline__ void pt_sweep(const GridItem &G, long p, long sy, long sz,
-                                         unsigned long long *__restrict__ ncount)
+template <int OP, typename PU, typename PF>
+__device__ __forceinline__ void sweep_node(PU u, PF F, long p, long sy, long sz, double s,
+                                           double hk, int slot,
+                                           unsigned long long *__restrict__ ncount)
 {
-    double *u = static_cast<double *>(G.p[0]);
-    const double *F = static_cast<const double *>(G.p[1]);
     if (OP == OP_MA) {
-        const Hess g = hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s);
+        const Hess g = hessian_at(u, p, 1, sy, sz, s, 0.25 * s);
         bool nc = false;
-        u[p] = ma_point_update(g, u[p], F[p], G.hk, nc);
+        u[p] = ma_point_update(g, u[p], F[p], hk, nc);
         if (nc)
-            atomicAdd(ncount + G.slot, 1ull);
+            atomicAdd(ncount + slot, 1ull);
     } else {
-        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, G.s), u[p], F[p], G.hk);
+        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, s), u[p], F[p], hk);
     }
 }
 
-template <int OP>
-__device__ __forceinline__ double pt_resid(const GridItem &G, long p, long sy, long sz)
+template <int OP, typename PU, typename PF>
+__device__ __forceinline__ double resid_node(PU u, PF F, long p, long sy, long sz, double s)
 {
-    const double *u = static_cast<const double *>(G.p[0]);
-    const double *F = static_cast<const double *>(G.p[1]);
     if (OP == OP_MA)
-        return F[p] - det3(hessian_at(u, p, 1, sy, sz, G.s, 0.25 * G.s));
-    return F[p] - laplacian_at(u, p, 1, sy, sz, G.s);
+        return F[p] - det3(hessian_at(u, p, 1, sy, sz, s, 0.25 * s));
+    return F[p] - laplacian_at(u, p, 1, sy, sz, s);
 }
 
-// FAS restriction at coarse node (I, J, K) of the fine grid G.n: injection
+// FAS restriction at coarse node (I, J, K) of the fine grid nf: injection
 // of u into w_H and u_H, and b_H = S_H(w_H) + I_h^H r at coarse interior
 // nodes (Algorithm 1, step 3).
-template <int OP, int RMODE>
-__device__ __forceinline__ void pt_restrict(const GridItem &G, int I, int J, int K)
+template <int OP, int RMODE, typename PU, typename PR, typename PO>
+__device__ __forceinline__ void restrict_node(int nf, int I, int J, int K, PU uf, PR rf, PO wc,
+                                              PO uc, PO bc)
 {
-    const int nf = G.n, nc = nf / 2;
-    const double *uf = static_cast<const double *>(G.p[0]);
-    const double *rf = static_cast<const double *>(G.p[1]);
+    const int nc = nf / 2;
     const long fy = nf + 1, fz = fy * fy, cy = nc + 1, cz = cy * cy;
     const long f = 2 * I + fy * (2 * J) + fz * (2 * K);
     const long c = I + cy * J + cz * K;
     const double v = uf[f];
-    static_cast<double *>(G.p[2])[c] = v;
-    static_cast<double *>(G.p[3])[c] = v;
+    wc[c] = v;
+    uc[c] = v;
     double b = 0.0;
     if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
         double rh;
@@ -104,21 +102,20 @@ __device__ __forceinline__ void pt_restrict(const GridItem &G, int I, int J, int
             sh = laplacian_at(uf, f, 2, 2 * fy, 2 * fz, sc);
         b = sh + rh;
     }
-    static_cast<double *>(G.p[4])[c] = b;
+    bc[c] = b;
 }
 
 // Trilinear prolongation of the coarse correction (u_H - w_H) added at
-// fine interior node (i, j, k) (Algorithm 1, step 5).  T: double or float.
-template <typename T>
-__device__ __forceinline__ void pt_prolong(const GridItem &G, int i, int j, int k)
+// fine interior node (i, j, k) of the fine grid nf (Algorithm 1, step 5).
+// T: double or float.
+template <typename T, typename PF, typename PC>
+__device__ __forceinline__ void prolong_node(int nf, int i, int j, int k, PF uf, PC uc, PC wc)
 {
-    const int nf = G.n, nc = nf / 2;
+    const int nc = nf / 2;
     const long sy = nf + 1, sz = sy * sy, cy = nc + 1, cz = cy * cy;
     const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
     const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
     const long p = i + sy * j + sz * k;
-    const T *uc = static_cast<const T *>(G.p[1]);
-    const T *wc = static_cast<const T *>(G.p[2]);
     const T one = T(1), half = T(0.5);
     const T wi = (i & 1) ? half : one, wj = (j & 1) ? half : one, wk = (k & 1) ? half : one;
     T d = T(0);
@@ -128,7 +125,37 @@ __device__ __forceinline__ void pt_prolong(const GridItem &G, int i, int j, int 
                 const long q = (I0 + a) + cy * (J0 + b) + cz * (K0 + c);
                 d += (wk * wj * wi) * (uc[q] - wc[q]);
             }
-    static_cast<T *>(G.p[0])[p] += d;
+    uf[p] += d;
+}
+
+// The same phases on a grid of a device table (global memory).
+template <int OP>
+__device__ __forceinline__ void pt_sweep(const GridItem &G, long p, long sy, long sz,
+                                         unsigned long long *__restrict__ ncount)
+{
+    sweep_node<OP>(gptr<double>(G.p[0]), gptr<const double>(G.p[1]), p, sy, sz, G.s, G.hk,
+                   G.slot, ncount);
+}
+
+template <int OP>
+__device__ __forceinline__ double pt_resid(const GridItem &G, long p, long sy, long sz)
+{
+    return resid_node<OP>(gptr<const double>(G.p[0]), gptr<const double>(G.p[1]), p, sy, sz,
+                          G.s);
+}
+
+template <int OP, int RMODE>
+__device__ __forceinline__ void pt_restrict(const GridItem &G, int I, int J, int K)
+{
+    restrict_node<OP, RMODE>(G.n, I, J, K, gptr<const double>(G.p[0]),
+                             gptr<const double>(G.p[1]), gptr<double>(G.p[2]),
+                             gptr<double>(G.p[3]), gptr<double>(G.p[4]));
+}
+
+template <typename T>
+__device__ __forceinline__ void pt_prolong(const GridItem &G, int i, int j, int k)
+{
+    prolong_node<T>(G.n, i, j, k, gptr<T>(G.p[0]), gptr<const T>(G.p[1]), gptr<const T>(G.p[2]));
 }
 
 __device__ __forceinline__ void pt_msweep(const GridItem &G, long p, long sy, long sz,
@@ -242,7 +269,7 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
             const long p = i + sy * j + sz * k;
             rv = pt_resid<OP>(G, p, sy, sz);
             if (KIND == LK_RESIDUAL)
-                static_cast<double *>(G.p[2])[p] = rv;
+                gptr<double>(G.p[2])[p] = rv;
             if (KIND == LK_RES32)
                 static_cast<float *>(G.p[2])[p] = float(rv);
         }
@@ -369,29 +396,45 @@ __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__rest
 // most (n/2)^2 (n-1) or (n/2)^3 candidates), since the rows of a coarse
 // grid are far shorter than a wavefront.
 // ---------------------------------------------------------------------------
+// Candidates of one colour class of an n grid: q < colour_count(n) -> node
+// (i, j, k); true when the node is interior.
+template <int ORDER>
+__device__ __forceinline__ int colour_count(int n)
+{
+    const int hn = n / 2;
+    return ORDER == 0 ? hn * hn * (n - 1) : hn * hn * hn;
+}
+
+template <int ORDER>
+__device__ __forceinline__ bool colour_node(int n, int color, int q, int &i, int &j, int &k)
+{
+    const int hn = n / 2;
+    const int ii = q % hn, r = q / hn;
+    const int jj = r % hn, kk = r / hn;
+    if (ORDER == 0) {
+        const int c0 = color & 1, c1 = color >> 1;
+        k = 1 + kk;
+        j = (((c0 + c1 + k) & 1) ? 1 : 2) + 2 * jj;
+        i = (((c0 + j) & 1) ? 1 : 2) + 2 * ii;
+    } else {
+        i = ((color & 1) ? 1 : 2) + 2 * ii;
+        j = (((color >> 1) & 1) ? 1 : 2) + 2 * jj;
+        k = (((color >> 2) & 1) ? 1 : 2) + 2 * kk;
+    }
+    return i <= n - 1 && j <= n - 1 && k <= n - 1;
+}
+
 template <int OP, bool MIXED, int ORDER>
 __device__ __forceinline__ void tail_sweep(const GridItem &G, int color,
                                            unsigned long long *__restrict__ ncount,
                                            unsigned long long *__restrict__ nfall)
 {
-    const int n = G.n, hn = n / 2;
+    const int n = G.n;
     const long sy = n + 1, sz = sy * sy;
-    const int cnt = ORDER == 0 ? hn * hn * (n - 1) : hn * hn * hn;
+    const int cnt = colour_count<ORDER>(n);
     for (int q = threadIdx.x; q < cnt; q += kTailThreads) {
-        const int ii = q % hn, r = q / hn;
-        const int jj = r % hn, kk = r / hn;
         int i, j, k;
-        if (ORDER == 0) {
-            const int c0 = color & 1, c1 = color >> 1;
-            k = 1 + kk;
-            j = (((c0 + c1 + k) & 1) ? 1 : 2) + 2 * jj;
-            i = (((c0 + j) & 1) ? 1 : 2) + 2 * ii;
-        } else {
-            i = ((color & 1) ? 1 : 2) + 2 * ii;
-            j = (((color >> 1) & 1) ? 1 : 2) + 2 * jj;
-            k = (((color >> 2) & 1) ? 1 : 2) + 2 * kk;
-        }
-        if (i <= n - 1 && j <= n - 1 && k <= n - 1) {
+        if (colour_node<ORDER>(n, color, q, i, j, k)) {
             const long p = i + sy * j + sz * k;
             if (MIXED)
                 pt_msweep(G, p, sy, sz, ncount, nfall);
@@ -484,6 +527,114 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailList *__restric
                 __syncthreads();
             }
     }
+}
+
+// LDS form of the coarse-level kernel (FP64 operators only): the solve's
+// coarse levels live in LDS for the whole launch -- the top level's u and
+// b are loaded at entry and its u is written back at exit -- so every phase
+// reads and writes LDS and the barriers order LDS only.  The phases and the
+// per-node arithmetic are those of k_tail, so the results are bitwise the
+// same.
+template <int OP, int ORDER, int RMODE>
+__global__ __launch_bounds__(kTailLdsThreads) void k_tail_lds(
+    const TailList *__restrict__ T, int nu1, int nu2, int nu0,
+    unsigned long long *__restrict__ ncount)
+{
+    __shared__ double S[kTailLdsDoubles];
+    if (int(blockIdx.x) >= T->nsolves)
+        return;
+    const TailEntry &E = T->e[blockIdx.x];
+    const int L = E.nlev;
+    const int tid = int(threadIdx.x);
+    constexpr int NT = kTailLdsThreads;
+    constexpr int colours = ORDER == 0 ? 4 : 8;
+    auto npts3 = [](int n) { return (n + 1) * (n + 1) * (n + 1); };
+    {
+        const int N = npts3(E.lv[0].sw.n);
+        const auto gu = gptr<const double>(E.lv[0].sw.p[0]);
+        const auto gb = gptr<const double>(E.lv[0].sw.p[1]);
+        double *u = S + E.L.u[0], *b = S + E.L.b[0];
+        for (int q = tid; q < N; q += NT) {
+            u[q] = gu[q];
+            b[q] = gb[q];
+        }
+    }
+    lds_barrier();
+    auto sweep = [&](int l) {
+        const GridItem &G = E.lv[l].sw;
+        const int n = G.n;
+        const long sy = n + 1, sz = sy * sy;
+        double *u = S + E.L.u[l];
+        const double *b = S + E.L.b[l];
+        const int cnt = colour_count<ORDER>(n);
+        for (int c = 0; c < colours; ++c) {
+            for (int q = tid; q < cnt; q += NT) {
+                int i, j, k;
+                if (colour_node<ORDER>(n, c, q, i, j, k))
+                    sweep_node<OP>(u, b, i + sy * j + sz * k, sy, sz, G.s, G.hk, G.slot, ncount);
+            }
+            lds_barrier();
+        }
+    };
+    for (int l = 0; l < L; ++l) {
+        const int cnt = l < L - 1 ? nu1 : nu0;
+        for (int s = 0; s < cnt; ++s)
+            sweep(l);
+        if (l < L - 1) {
+            const int n = E.lv[l].sw.n, m = n - 1;
+            const long sy = n + 1, sz = sy * sy;
+            const double *u = S + E.L.u[l], *b = S + E.L.b[l];
+            double *r = S + E.L.r[l];
+            for (int q = tid; q < m * m * m; q += NT) {
+                const int i = 1 + q % m, rr = q / m;
+                const int j = 1 + rr % m, k = 1 + rr / m;
+                const long p = i + sy * j + sz * k;
+                r[p] = resid_node<OP>(u, b, p, sy, sz, E.lv[l].sw.s);
+            }
+            lds_barrier();
+            const int mc = n / 2 + 1;
+            for (int q = tid; q < mc * mc * mc; q += NT) {
+                const int I = q % mc, rr = q / mc;
+                const int J = rr % mc, K = rr / mc;
+                restrict_node<OP, RMODE>(n, I, J, K, static_cast<const double *>(u),
+                                         static_cast<const double *>(r), S + E.L.w[l + 1],
+                                         S + E.L.u[l + 1], S + E.L.b[l + 1]);
+            }
+            lds_barrier();
+        }
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        const int n = E.lv[l].sw.n, m = n - 1;
+        double *u = S + E.L.u[l];
+        const double *uc = S + E.L.u[l + 1], *wc = S + E.L.w[l + 1];
+        for (int q = tid; q < m * m * m; q += NT) {
+            const int i = 1 + q % m, rr = q / m;
+            const int j = 1 + rr % m, k = 1 + rr / m;
+            prolong_node<double>(n, i, j, k, u, uc, wc);
+        }
+        lds_barrier();
+        for (int s = 0; s < nu2; ++s)
+            sweep(l);
+    }
+    {
+        const int N = npts3(E.lv[0].sw.n);
+        const auto gu = gptr<double>(E.lv[0].sw.p[0]);
+        const double *u = S + E.L.u[0];
+        for (int q = tid; q < N; q += NT)
+            gu[q] = u[q];
+    }
+}
+
+template <int OP, int ORDER>
+hipError_t launch_tail_lds_t(hipStream_t st, int rmode, const TailList *T, int blocks, int nu1,
+                             int nu2, int nu0, unsigned long long *nc)
+{
+    const dim3 grid(blocks), block(kTailLdsThreads);
+    if (rmode == 0)
+        hipLaunchKernelGGL((k_tail_lds<OP, ORDER, 0>), grid, block, 0, st, T, nu1, nu2, nu0, nc);
+    else
+        hipLaunchKernelGGL((k_tail_lds<OP, ORDER, 1>), grid, block, 0, st, T, nu1, nu2, nu0, nc);
+    return hipGetLastError();
 }
 
 template <int KIND, int OP>
@@ -635,6 +786,21 @@ hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const Tai
     default:
         return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_tail_lds(hipStream_t st, int mode, int order, int rmode, const TailList *T,
+                           int blocks, int nu1, int nu2, int nu0, unsigned long long *nc)
+{
+    if (blocks <= 0 || blocks > kMaxGrids)
+        return hipErrorInvalidValue;
+    if (mode != Engine::MODE_MA && mode != Engine::MODE_LAP)
+        return hipErrorInvalidValue;
+    const bool ma = mode == Engine::MODE_MA;
+    if (order == 0)
+        return ma ? launch_tail_lds_t<OP_MA, 0>(st, rmode, T, blocks, nu1, nu2, nu0, nc)
+                  : launch_tail_lds_t<OP_LAP, 0>(st, rmode, T, blocks, nu1, nu2, nu0, nc);
+    return ma ? launch_tail_lds_t<OP_MA, 1>(st, rmode, T, blocks, nu1, nu2, nu0, nc)
+              : launch_tail_lds_t<OP_LAP, 1>(st, rmode, T, blocks, nu1, nu2, nu0, nc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1024,7 +1190,39 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
     if (size_t(pnext) > partials_cap_)
         return fail(MA_ERR_ARG, "partial-sum buffer too small for the batch");
 
-    // coarse-level table, after the lists
+    // coarse-level table, after the lists.  The LDS form of the coarse-level
+    // kernel runs when every solve's coarse levels fit its LDS (decided over
+    // all solves of the engine, so it does not change when solves pause).
+    auto lds_layout = [&](int i, TailLds &Ld) {
+        const int m = multiblock_levels(i), L = levels(i);
+        int off = 0;
+        for (int l = 0; l < kMaxTail; ++l) {
+            Ld.u[l] = Ld.b[l] = Ld.w[l] = Ld.r[l] = -1;
+            if (l >= L - m)
+                continue;
+            const int N = int(npts(solves_[i].s->lv[m + l].n));
+            Ld.u[l] = off;
+            off += N;
+            Ld.b[l] = off;
+            off += N;
+            if (l > 0) {
+                Ld.w[l] = off;
+                off += N;
+            }
+            if (l < L - m - 1) {
+                Ld.r[l] = off;
+                off += N;
+            }
+        }
+        return off <= kTailLdsDoubles;
+    };
+    tail_lds_ = !mixed;
+    for (int i = 0; i < S && tail_lds_; ++i) {
+        if (!solves_[i].s || levels(i) - multiblock_levels(i) <= 0)
+            continue;
+        TailLds Ld;
+        tail_lds_ = levels(i) - multiblock_levels(i) <= kMaxTail && lds_layout(i, Ld);
+    }
     toff_ = hbuf_.size();
     hbuf_.resize(toff_ + tail_bytes(S), 0);
     {
@@ -1043,6 +1241,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                 continue;
             TailEntry &E = T->e[nt++];
             E.nlev = L - m;
+            E.lds = lds_layout(i, E.L) ? 1 : 0;
             for (int l = 0; l < L - m; ++l) {
                 const int d = m + l;
                 TailLevel &V = E.lv[l];
@@ -1262,7 +1461,11 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
             MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
             MA_TRY(go(mixed ? LK_MRESTRICT : LK_RESTRICT, rst_[d], 0));
         }
-        if (tail_blocks_ > 0)
+        if (tail_blocks_ > 0 && tail_lds_)
+            E_HIP(launch_tail_lds(stream_, int(mode), order_, rmode_,
+                                  reinterpret_cast<const TailList *>(dl_ + toff_), tail_blocks_,
+                                  nu1_, nu2_, nu0_, dcount_));
+        else if (tail_blocks_ > 0)
             E_HIP(launch_tail(stream_, int(mode), order_, rmode_,
                               reinterpret_cast<const TailList *>(dl_ + toff_), tail_blocks_, nu1_,
                               nu2_, nu0_, dcount_, dfall_));
@@ -1303,6 +1506,7 @@ std::vector<int> Engine::shape() const
     s.push_back(int(stride_));
     s.push_back(int(toff_));
     s.push_back(tail_blocks_);
+    s.push_back(tail_lds_ ? 1 : 0);
     s.push_back(strip_rows_);
     s.push_back(int(loff_.size()));
     s.insert(s.end(), lgrid_.begin(), lgrid_.end());
