@@ -64,6 +64,26 @@ constexpr size_t list_bytes(int ngrids) { return 16 + sizeof(GridItem) * size_t(
 struct TailLevel {
     GridItem sw, res, rst, pro;
 };
+// One grid of a fused residual-restriction launch: fine grid n (u, F) and
+// the coarse arrays w, u, b of n/2; tiles of kRrTile^3 coarse nodes.
+constexpr int kRrTile = 4;
+struct RrGrid {
+    const double *uf, *F;
+    double *wc, *uc, *bc;
+    int n;
+    int tiles_x, tiles_y, tiles_z;
+    int start;      // first tile of this grid in the launch
+    int pad;
+    double s;       // 1/h^2 of the fine grid
+};
+struct RrList {
+    int ngrids;
+    int total;
+    int pad[2];
+    RrGrid g[kMaxGrids];
+};
+constexpr size_t rr_list_bytes(int ngrids) { return 16 + sizeof(RrGrid) * size_t(ngrids); }
+
 // LDS form: offsets (in doubles) of each level's u, b, w, r in LDS, -1
 // where the level has no such array (w above the first level, r on the
 // coarsest).
@@ -117,6 +137,8 @@ void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *
 hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const TailList *T,
                        int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount,
                        unsigned long long *nfall);
+// fused residual + restriction (op: OP_MA / OP_LAP), one block per tile
+hipError_t launch_rrestrict(hipStream_t st, int op, int rmode, const RrList *L, int blocks);
 // the LDS form (MODE_MA, MODE_LAP; every entry with lds = 1)
 hipError_t launch_tail_lds(hipStream_t st, int mode, int order, int rmode, const TailList *T,
                            int blocks, int nu1, int nu2, int nu0, unsigned long long *ncount);
@@ -218,6 +240,11 @@ class Engine {
     std::vector<int> fscfg_;               // block shape per FsList
     size_t fs_stride_ = 0;
     std::vector<int> res_, rst_, pro_, inj_;
+    // fused residual-restriction list of each depth (-1: separate launches)
+    std::vector<int> rr_;
+    std::vector<size_t> rroff_;            // byte offset of each RrList
+    std::vector<int> rrblocks_;            // blocks per RrList launch
+    size_t rr_stride_ = 0;
     int norm_ = -1, accum_ = -1, zero_ = -1;
 
     double *partials_ = nullptr;

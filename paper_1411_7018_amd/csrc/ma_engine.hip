@@ -55,17 +55,54 @@ __device__ __forceinline__ void sweep_node(PU u, PF F, long p, long sy, long sz,
     }
 }
 
+// r = F - S(u) at node p of u with right-hand side value Fv.
+template <int OP, typename PU>
+__device__ __forceinline__ double resid_val(PU u, long p, long sy, long sz, double s, double Fv)
+{
+    if (OP == OP_MA)
+        return Fv - det3(hessian_at(u, p, 1, sy, sz, s, 0.25 * s));
+    return Fv - laplacian_at(u, p, 1, sy, sz, s);
+}
+
 template <int OP, typename PU, typename PF>
 __device__ __forceinline__ double resid_node(PU u, PF F, long p, long sy, long sz, double s)
 {
+    return resid_val<OP>(u, p, sy, sz, s, F[p]);
+}
+
+// b_H at a coarse interior node: S_H(w_H) + I_h^H r (Algorithm 1, step 3),
+// with w_H the injection of u.  The coarse node sits at fine index fu of uf
+// (strides uy, uz) and fr of rf (strides ry, rz); sc = 1/H^2.
+template <int OP, int RMODE, typename PU, typename PR>
+__device__ __forceinline__ double restrict_b(PU uf, long fu, long uy, long uz, PR rf, long fr,
+                                             long ry, long rz, double sc)
+{
+    double rh;
+    if (RMODE == 0) {
+        const double w[3] = {0.25, 0.5, 0.25};
+        rh = 0.0;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    rh += (w[dz + 1] * w[dy + 1] * w[dx + 1]) * rf[fr + dx + ry * dy + rz * dz];
+    } else {
+        rh = (6.0 * rf[fr] + (rf[fr - 1] + rf[fr + 1]) + (rf[fr - ry] + rf[fr + ry])
+              + (rf[fr - rz] + rf[fr + rz])) / 12.0;
+    }
+    double sh;
     if (OP == OP_MA)
-        return F[p] - det3(hessian_at(u, p, 1, sy, sz, s, 0.25 * s));
-    return F[p] - laplacian_at(u, p, 1, sy, sz, s);
+        sh = det3(hessian_at(uf, fu, 2, 2 * uy, 2 * uz, sc, 0.25 * sc));
+    else
+        sh = laplacian_at(uf, fu, 2, 2 * uy, 2 * uz, sc);
+    return sh + rh;
 }
 
 // FAS restriction at coarse node (I, J, K) of the fine grid nf: injection
 // of u into w_H and u_H, and b_H = S_H(w_H) + I_h^H r at coarse interior
-// nodes (Algorithm 1, step 3).
+// nodes, 0 on the boundary (Algorithm 1, step 3).
 template <int OP, int RMODE, typename PU, typename PR, typename PO>
 __device__ __forceinline__ void restrict_node(int nf, int I, int J, int K, PU uf, PR rf, PO wc,
                                               PO uc, PO bc)
@@ -78,30 +115,8 @@ __device__ __forceinline__ void restrict_node(int nf, int I, int J, int K, PU uf
     wc[c] = v;
     uc[c] = v;
     double b = 0.0;
-    if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1) {
-        double rh;
-        if (RMODE == 0) {
-            const double w[3] = {0.25, 0.5, 0.25};
-            rh = 0.0;
-#pragma unroll
-            for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx)
-                        rh += (w[dz + 1] * w[dy + 1] * w[dx + 1]) * rf[f + dx + fy * dy + fz * dz];
-        } else {
-            rh = (6.0 * rf[f] + (rf[f - 1] + rf[f + 1]) + (rf[f - fy] + rf[f + fy])
-                  + (rf[f - fz] + rf[f + fz])) / 12.0;
-        }
-        const double sc = double(nc) * double(nc);
-        double sh;
-        if (OP == OP_MA)
-            sh = det3(hessian_at(uf, f, 2, 2 * fy, 2 * fz, sc, 0.25 * sc));
-        else
-            sh = laplacian_at(uf, f, 2, 2 * fy, 2 * fz, sc);
-        b = sh + rh;
-    }
+    if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1)
+        b = restrict_b<OP, RMODE>(uf, f, fy, fz, rf, f, fy, fz, double(nc) * double(nc));
     bc[c] = b;
 }
 
@@ -529,6 +544,99 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailList *__restric
     }
 }
 
+// Fused residual and FAS restriction (FP64 operators): one workgroup per
+// TC^3 block of coarse nodes.  It loads the fine u it needs into LDS,
+// computes r = F - S(u) once per fine node of the block's footprint into
+// LDS, and restricts from LDS: injection into w_H and u_H and b_H =
+// S_H(w_H) + I_h^H r.  The fine residual never goes through memory, and the
+// arithmetic is that of resid_node and restrict_node, so the coarse arrays
+// are bitwise those of the separate residual and restriction launches.
+template <int TC>
+struct RrShape {
+    static constexpr int RU = 2 * TC + 3;    // u footprint per side (fine nodes)
+    static constexpr int RR = 2 * TC + 1;    // r footprint per side
+    static constexpr int NU = RU * RU * RU, NR = RR * RR * RR;
+};
+
+template <int OP, int RMODE, int TC, int NT>
+__global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst)
+{
+    using R = RrShape<TC>;
+    constexpr int RU = R::RU, RR = R::RR;
+    __shared__ double su[R::NU];
+    __shared__ double sr[R::NR];
+    const int total = Lst->total;
+    const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
+    if (t >= total)
+        return;
+    const int ng = Lst->ngrids;
+    int g = 0;
+    while (g + 1 < ng && Lst->g[g + 1].start <= t)
+        ++g;
+    const RrGrid &G = Lst->g[g];
+    const int tile = t - G.start;
+    const int nf = G.n, nc = nf / 2;
+    const int tx = tile % G.tiles_x, rest = tile / G.tiles_x;
+    const int ty = rest % G.tiles_y, tz = rest / G.tiles_y;
+    const int I0 = tx * TC, J0 = ty * TC, K0 = tz * TC;
+    const int ux0 = 2 * I0 - 2, uy0 = 2 * J0 - 2, uz0 = 2 * K0 - 2;   // u footprint origin
+    const long fy = nf + 1, fz = fy * fy;
+    const int tid = int(threadIdx.x);
+    const auto uf = to_global(G.uf);
+    const auto F = to_global(G.F);
+    for (int el = tid; el < R::NU; el += NT) {
+        const int lz = el / (RU * RU), rem = el - lz * (RU * RU);
+        const int ly = rem / RU, lx = rem - ly * RU;
+        const int gx = ux0 + lx, gy = uy0 + ly, gz = uz0 + lz;
+        const bool in = gx >= 0 && gx <= nf && gy >= 0 && gy <= nf && gz >= 0 && gz <= nf;
+        su[el] = in ? uf[gx + fy * gy + fz * gz] : 0.0;
+    }
+    lds_barrier();
+    // r on the fine interior nodes of the footprint (origin ux0 + 1)
+    for (int el = tid; el < R::NR; el += NT) {
+        const int lz = el / (RR * RR), rem = el - lz * (RR * RR);
+        const int ly = rem / RR, lx = rem - ly * RR;
+        const int gx = ux0 + 1 + lx, gy = uy0 + 1 + ly, gz = uz0 + 1 + lz;
+        double rv = 0.0;
+        if (gx >= 1 && gx <= nf - 1 && gy >= 1 && gy <= nf - 1 && gz >= 1 && gz <= nf - 1) {
+            const long pu = (lx + 1) + RU * (ly + 1) + long(RU * RU) * (lz + 1);
+            rv = resid_val<OP>(static_cast<const double *>(su), pu, RU, RU * RU, G.s,
+                               F[gx + fy * gy + fz * gz]);
+        }
+        sr[el] = rv;
+    }
+    lds_barrier();
+    const long cy = nc + 1, cz = cy * cy;
+    const auto wc = to_global(G.wc);
+    const auto uc = to_global(G.uc);
+    const auto bc = to_global(G.bc);
+    const double sc = double(nc) * double(nc);
+    for (int el = tid; el < TC * TC * TC; el += NT) {
+        const int a = el % TC, b2 = el / TC;
+        const int I = I0 + a, J = J0 + b2 % TC, K = K0 + b2 / TC;
+        if (I > nc || J > nc || K > nc)
+            continue;
+        const long fu = (2 * I - ux0) + RU * (2 * J - uy0) + long(RU * RU) * (2 * K - uz0);
+        const long fr = (2 * I - ux0 - 1) + RR * (2 * J - uy0 - 1) + long(RR * RR) * (2 * K - uz0 - 1);
+        const long c = I + cy * J + cz * K;
+        const double v = su[fu];
+        wc[c] = v;
+        uc[c] = v;
+        double bv = 0.0;
+        if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1)
+            bv = restrict_b<OP, RMODE>(static_cast<const double *>(su), fu, RU, RU * RU,
+                                       static_cast<const double *>(sr), fr, RR, RR * RR, sc);
+        bc[c] = bv;
+    }
+}
+
+template <int OP, int RMODE>
+hipError_t launch_rr_t(hipStream_t st, const RrList *L, int blocks)
+{
+    hipLaunchKernelGGL((k_rrestrict<OP, RMODE, kRrTile, 256>), dim3(blocks), dim3(256), 0, st, L);
+    return hipGetLastError();
+}
+
 // LDS form of the coarse-level kernel (FP64 operators only): the solve's
 // coarse levels live in LDS for the whole launch -- the top level's u and
 // b are loaded at entry and its u is written back at exit -- so every phase
@@ -786,6 +894,15 @@ hipError_t launch_tail(hipStream_t st, int mode, int order, int rmode, const Tai
     default:
         return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_rrestrict(hipStream_t st, int op, int rmode, const RrList *L, int blocks)
+{
+    if (blocks <= 0)
+        return hipErrorInvalidValue;
+    if (op == OP_MA)
+        return rmode == 0 ? launch_rr_t<OP_MA, 0>(st, L, blocks) : launch_rr_t<OP_MA, 1>(st, L, blocks);
+    return rmode == 0 ? launch_rr_t<OP_LAP, 0>(st, L, blocks) : launch_rr_t<OP_LAP, 1>(st, L, blocks);
 }
 
 hipError_t launch_tail_lds(hipStream_t st, int mode, int order, int rmode, const TailList *T,
@@ -1334,6 +1451,54 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         }
     }
 
+    // Fused residual-restriction lists, after the block-sweep lists: every
+    // depth's residual and restriction in one launch (FP64 operators; the
+    // COLOR smoother keeps the separate launches as the reference form).
+    rroff_.clear();
+    rrblocks_.clear();
+    rr_stride_ = rr_list_bytes(S);
+    rr_.assign(D_, -1);
+    if (!mixed && smoother_ != MA_SMOOTHER_COLOR) {
+        for (int d = 0; d < D_; ++d) {
+            RrList Lr;
+            Lr.ngrids = 0;
+            Lr.pad[0] = Lr.pad[1] = 0;
+            int start = 0;
+            long bound = 0;
+            for (int i = 0; i < S; ++i) {
+                if (!solves_[i].s || multiblock_levels(i) <= d || d >= levels(i) - 1)
+                    continue;
+                const ma_solver *sv = solves_[i].s;
+                RrGrid G;
+                std::memset(&G, 0, sizeof(G));
+                G.uf = level_u(i, d, mode);
+                G.F = level_F(i, d, mode);
+                G.wc = sv->lv[d + 1].w;
+                G.uc = sv->lv[d + 1].u;
+                G.bc = sv->lv[d + 1].b;
+                G.n = sv->lv[d].n;
+                const int tc = (G.n / 2 + 1 + kRrTile - 1) / kRrTile;
+                G.tiles_x = G.tiles_y = G.tiles_z = tc;
+                G.s = double(G.n) * double(G.n);
+                bound += long(tc) * tc * tc;
+                if (!active[i])
+                    continue;
+                G.start = start;
+                start += tc * tc * tc;
+                Lr.g[Lr.ngrids++] = G;
+            }
+            Lr.total = start;
+            if (bound == 0)
+                continue;
+            rr_[d] = int(rroff_.size());
+            const size_t off = hbuf_.size();
+            rroff_.push_back(off);
+            rrblocks_.push_back(int(bound));
+            hbuf_.resize(off + rr_stride_, 0);
+            std::memcpy(hbuf_.data() + off, &Lr, rr_list_bytes(Lr.ngrids));
+        }
+    }
+
     prof_bytes_tick_ = 0.0;
     prof_launches_tick_ = 0;
     for (int i = 0; i < S; ++i)
@@ -1458,8 +1623,14 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
             MA_TRY(sweeps(swd_[d], bsd_[d]));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
-            MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
-            MA_TRY(go(mixed ? LK_MRESTRICT : LK_RESTRICT, rst_[d], 0));
+            if (rr_[d] >= 0) {
+                E_HIP(launch_rrestrict(stream_, op, rmode_,
+                                       reinterpret_cast<const RrList *>(dl_ + rroff_[rr_[d]]),
+                                       rrblocks_[rr_[d]]));
+            } else {
+                MA_TRY(go(mixed ? LK_MRESIDUAL : LK_RESIDUAL, res_[d], 0));
+                MA_TRY(go(mixed ? LK_MRESTRICT : LK_RESTRICT, rst_[d], 0));
+            }
         }
         if (tail_blocks_ > 0 && tail_lds_)
             E_HIP(launch_tail_lds(stream_, int(mode), order_, rmode_,
@@ -1515,6 +1686,9 @@ std::vector<int> Engine::shape() const
     s.push_back(int(fs_stride_));
     s.insert(s.end(), fsblocks_.begin(), fsblocks_.end());
     s.insert(s.end(), fscfg_.begin(), fscfg_.end());
+    s.push_back(int(rroff_.size()));
+    s.push_back(rroff_.empty() ? 0 : int(rroff_[0]));
+    s.insert(s.end(), rrblocks_.begin(), rrblocks_.end());
     return s;
 }
 
