@@ -33,7 +33,7 @@ import torch
 BLOCKS = (4096, 8192, 16384, 32768, 65536)
 COARSE = (0, 8, 16, 32)
 STRIPS = (8, 32, 128, 4096)
-BLOCK_N = (-1, 32, 64, 128)
+BLOCK_N = (-1, 32, 64)
 
 
 @dataclasses.dataclass

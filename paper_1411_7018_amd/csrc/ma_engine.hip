@@ -630,10 +630,17 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
     }
 }
 
+// Threads per tile: 256 when the launch has many tiles (throughput), 512
+// when it has few (one tile's residual rounds are the latency).
+constexpr int kRrManyTiles = 2048;
+
 template <int OP, int RMODE>
 hipError_t launch_rr_t(hipStream_t st, const RrList *L, int blocks)
 {
-    hipLaunchKernelGGL((k_rrestrict<OP, RMODE, kRrTile, 256>), dim3(blocks), dim3(256), 0, st, L);
+    if (blocks >= kRrManyTiles)
+        hipLaunchKernelGGL((k_rrestrict<OP, RMODE, kRrTile, 256>), dim3(blocks), dim3(256), 0, st, L);
+    else
+        hipLaunchKernelGGL((k_rrestrict<OP, RMODE, kRrTile, 512>), dim3(blocks), dim3(512), 0, st, L);
     return hipGetLastError();
 }
 
