@@ -69,13 +69,33 @@ def test_footprint_grows_with_n_and_rejects_invalid():
 def test_create_rejects_invalid_params_without_gpu():
     from paper_1411_7018_amd import _lib as L
     for field, val in (("n", 1), ("nu0", 0), ("order", 7), ("precision", 9),
-                       ("restriction", 5), ("inner_cycles", 0)):
+                       ("restriction", 5), ("inner_cycles", 0), ("smoother", 3),
+                       ("tile_config", 6), ("tile_config", -1), ("block_n", -2),
+                       ("coarse_n", 33), ("max_blocks", 12), ("strip_rows", 5000)):
         p = L.ma_params_default(16)
         setattr(p, field, val)
         with pytest.raises(L.MAError) as ei:
             L.ma_create(p, None)
         assert ei.value.status == L.MA_ERR_ARG
     assert "n must be" in L.ma_last_error(None) or L.ma_last_error(None)
+
+
+def test_launch_shape_defaults():
+    """The knobs that change only the launch structure default to automatic
+    (block sweeps on levels up to n = 64, coarse levels up to 16 in one
+    kernel), and block_n accepts -1 (never) .. 2048."""
+    from paper_1411_7018_amd import _lib as L
+    p = L.ma_params_default(128)
+    assert (p.smoother, p.tile_config, p.block_n) == (L.MA_SMOOTHER_AUTO, 0, 0)
+    assert (p.coarse_n, p.max_blocks, p.strip_rows) == (16, 0, 0)
+    for bn in (-1, 0, 32, 2048):
+        p.block_n = bn
+        assert L.ma_footprint_bytes(p) > 0
+    for tc in range(0, 6):
+        p.block_n, p.tile_config = 0, tc
+        assert L.ma_footprint_bytes(p) > 0
+    p.block_n = 2049
+    assert L.ma_footprint_bytes(p) == 0
 
 
 def test_null_handles_are_rejected():
