@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
     ap.add_argument("--budget-gb", type=float, default=None, help="served: HBM budget")
+    ap.add_argument("--lanes", default="65/129/257/385",
+                    help="served: size classes in points per side, '/' between classes and "
+                         "',' inside one (one resident batch, ticking on its own stream, per "
+                         "class); 'none' for a single batch")
     return ap.parse_args()
 
 
@@ -381,12 +385,17 @@ def run_served(args, precision):
             del s, u, f
         rate = 0.8 / tsvc
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else GpuBackend.budget_default()
+    lanes = None
+    if args.lanes and args.lanes != "none":
+        # classes of grid sizes in points per side (65, 129, ...); requests carry n
+        lanes = [[int(p) - 1 for p in c.split(",")] for c in args.lanes.split("/")]
     be = GpuBackend(precision=precision, tol=1e-8, max_slots=64)
     if warmup:
-        Server(be, budget).run(requests_from_trace(P.arrival_trace(warmup, rate, seed=4999)))
+        Server(be, budget, lanes=lanes).run(
+            requests_from_trace(P.arrival_trace(warmup, rate, seed=4999)))
     torch.cuda.synchronize()
     reqs = requests_from_trace(P.arrival_trace(count, rate, seed=5000))
-    srv = Server(be, budget, max_slots=64)
+    srv = Server(be, budget, max_slots=64, lanes=lanes)
     t0 = time.perf_counter()
     st = srv.run(reqs)
     torch.cuda.synchronize()
@@ -396,8 +405,10 @@ def run_served(args, precision):
     out["config"] = {
         "workload": f"served stream: {count} Poisson arrivals at {rate:.1f}/s, sizes "
                     f"65^3/129^3/257^3/385^3 (p=.4/.3/.2/.1), quadratic or exp-cos, tol 1e-8, "
-                    f"{precision}, HBM budget {budget / 2**30:.1f} GiB, continuous batching",
+                    f"{precision}, HBM budget {budget / 2**30:.1f} GiB, continuous batching, "
+                    + (f"lanes {args.lanes}" if lanes else "one resident batch"),
         "requests": count, "rate_per_s": rate, "budget_bytes": budget, "precision": precision,
+        "lanes": args.lanes if lanes else None,
         "latency": "completion - arrival"}
     out.update({"completed": st.completed, "rejected": st.rejected,
                 "mean_live": st.mean_live, "max_live": st.max_live, "queued": st.queued,

@@ -19,6 +19,12 @@ not fit otherwise.  Admission is first-come first-served; with
 start.  A request larger than the whole budget is rejected (status
 MA_ERR_OOM) and the rest are still served.
 
+With ``lanes`` the server keeps one resident batch per size class
+instead, each ticking on its own stream from its own host thread, so a small
+request advances at the pace of its own class rather than in lock step with
+the largest solve resident; the lanes share the HBM budget and the pool of
+idle hierarchies.
+
 Each solve's arithmetic and stopping decisions are its own (the engine
 batches launches, never data), so a result is bitwise the same alone and in
 any mix.  The scheduling logic talks to a small backend interface, so it
@@ -29,6 +35,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -86,10 +93,22 @@ class GpuBackend:
 
         return make_device(req.kind, req.n, req.seed)
 
-    def new_batch(self):
+    def new_batch(self, stream=None):
         from .batch import ResidentBatch
 
-        return ResidentBatch(self.max_slots)
+        return ResidentBatch(self.max_slots, stream=stream)
+
+    def new_stream(self):
+        import torch
+
+        return torch.cuda.Stream()
+
+    def on_stream(self, stream):
+        """Context in which the calls of a lane's thread order their work on
+        the lane's stream (request data included)."""
+        import torch
+
+        return torch.cuda.stream(stream)
 
     def add(self, batch, solver, u, f) -> int:
         return batch.add(solver, u, f, tol=self.tol)
@@ -123,9 +142,15 @@ class Stats:
 
 class Server:
     def __init__(self, backend, budget_bytes: int, max_slots: int = 64, pool: bool = True,
-                 skip_ahead: bool = False, keep_results: bool = False):
+                 skip_ahead: bool = False, keep_results: bool = False, lanes=None):
+        """lanes: None (one batch for all sizes) or a list of size classes,
+        each a collection of grid sizes n; a size in no class joins the
+        last one.  max_slots bounds each lane's batch."""
         if not 1 <= max_slots <= 64:
             raise ValueError("max_slots must be in 1..64")
+        self.lanes = [frozenset(int(n) for n in c) for c in lanes] if lanes else None
+        if self.lanes is not None and not self.lanes:
+            raise ValueError("lanes must name at least one size class")
         self.be = backend
         self.budget = int(budget_bytes)
         self.max_slots = max_slots
@@ -176,6 +201,8 @@ class Server:
 
     # -- main loop --------------------------------------------------------
     def run(self, requests, clock=time.perf_counter, sleep=time.sleep) -> Stats:
+        if self.lanes is not None and len(self.lanes) > 1:
+            return self._run_lanes(requests, clock, sleep)
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         pending = collections.deque(reqs)
         queue = collections.deque()
@@ -240,6 +267,9 @@ class Server:
         finally:
             self.batch.close()
             self.batch = None
+        return self._stats(reqs, ticks, live_sum, max_live, rejected, queued)
+
+    def _stats(self, reqs, ticks, live_sum, max_live, rejected, queued) -> Stats:
         done = [r for r in reqs if r.status == 0]
         lat = np.array([r.latency for r in done]) if done else np.zeros(1)
         t_first = reqs[0].t_arrival if reqs else 0.0
@@ -250,6 +280,146 @@ class Server:
                      mean=float(lat.mean()), solves_per_s=len(done) / makespan,
                      max_live=max_live, mean_live=live_sum / max(ticks, 1),
                      peak_bytes=self.peak, ticks=ticks, queued=queued)
+
+
+    # -- lanes ------------------------------------------------------------
+    def _lane_of(self, n: int) -> int:
+        for i, c in enumerate(self.lanes):
+            if n in c:
+                return i
+        return len(self.lanes) - 1
+
+    def _reserve(self, req: Request):
+        """Admission decision under the lock: ("ok", reused solver or None),
+        ("wait", None) or ("reject", None).  Budget and pool are updated
+        here; the solver and the data are made by the lane afterwards."""
+        n = req.n
+        arrays = self.be.array_bytes(n)
+        hier = self.be.hierarchy_bytes(n)
+        if arrays + hier > self.budget:
+            return "reject", None
+        reuse = next((k for k in self.idle if k[0] == n), None)
+        need = arrays + (0 if reuse else hier)
+        while self.used + need > self.budget and self._evict_one(reuse):
+            pass
+        if self.used + need > self.budget:
+            return "wait", None
+        self.used += need
+        self.peak = max(self.peak, self.used)
+        if reuse:
+            return "ok", self.idle.pop(reuse)
+        self.created += 1
+        return "ok", None
+
+    def _run_lanes(self, requests, clock, sleep) -> Stats:
+        reqs = sorted(requests, key=lambda r: r.t_arrival)
+        nl = len(self.lanes)
+        cv = threading.Condition()
+        queues = [collections.deque() for _ in range(nl)]
+        live_count = [0] * nl
+        arrived = {"all": False}
+        counts = {"ticks": 0, "live_sum": 0, "max_live": 0, "rejected": 0, "queued": 0}
+        errors = []
+        t0 = clock()
+
+        def lane(li):
+            stream = self.be.new_stream()
+            with self.be.on_stream(stream):
+                batch = self.be.new_batch(stream)
+                live = {}
+                try:
+                    while True:
+                        admitted = []
+                        with cv:
+                            now = clock() - t0
+                            q = queues[li]
+                            while q and len(live) + len(admitted) < self.max_slots:
+                                verdict, solver = self._reserve(q[0])
+                                if verdict == "wait":
+                                    # nothing live anywhere: only idle hierarchies
+                                    # could be in the way, and they were evicted
+                                    if not any(live_count) and not live and not admitted:
+                                        verdict = "reject"
+                                    else:
+                                        break
+                                req = q.popleft()
+                                if verdict == "reject":
+                                    req.status, req.t_admit, req.t_done = MA_ERR_OOM, now, now
+                                    counts["rejected"] += 1
+                                    continue
+                                req.t_admit = now
+                                if req.t_admit > req.t_arrival + 1e-3:
+                                    counts["queued"] += 1
+                                admitted.append((req, solver))
+                            live_count[li] = len(live) + len(admitted)
+                            if not live and not admitted:
+                                if arrived["all"] and not q:
+                                    return
+                                cv.wait(0.005)
+                                continue
+                        for req, solver in admitted:
+                            if solver is None:
+                                solver = self.be.new_solver(req.n)
+                            u, f = self.be.data(req)
+                            slot = self.be.add(batch, solver, u, f)
+                            live[slot] = (req, solver, u, f)
+                        done = batch.tick()
+                        tnow = clock() - t0
+                        retired = []
+                        for slot, code in done.items():
+                            req, solver, u, f = live.pop(slot)
+                            req.report = batch.report(slot)
+                            req.status = 0 if code == 1 else int(code)
+                            req.t_done = tnow
+                            if self.keep_results:
+                                req.u = u
+                            batch.remove(slot)
+                            retired.append((req, solver))
+                        with cv:
+                            counts["ticks"] += 1
+                            counts["live_sum"] += len(live) + len(retired)
+                            counts["max_live"] = max(counts["max_live"],
+                                                     sum(live_count))
+                            for req, solver in retired:
+                                self.used -= self.be.array_bytes(req.n)
+                                if self.pool:
+                                    self._serial += 1
+                                    self.idle[(req.n, self._serial)] = solver
+                                else:
+                                    self.used -= self.be.hierarchy_bytes(req.n)
+                            live_count[li] = len(live)
+                            cv.notify_all()
+                except BaseException as e:       # surfaced by run()
+                    with cv:
+                        errors.append(e)
+                        arrived["all"] = True
+                        cv.notify_all()
+                finally:
+                    batch.close()
+
+        threads = [threading.Thread(target=lane, args=(i,), daemon=True) for i in range(nl)]
+        for t in threads:
+            t.start()
+        try:
+            for req in reqs:
+                wait = req.t_arrival - (clock() - t0)
+                if wait > 0:
+                    sleep(wait)
+                with cv:
+                    if errors:
+                        break
+                    queues[self._lane_of(req.n)].append(req)
+                    cv.notify_all()
+        finally:
+            with cv:
+                arrived["all"] = True
+                cv.notify_all()
+            for t in threads:
+                t.join()
+        if errors:
+            raise errors[0]
+        return self._stats(reqs, counts["ticks"], counts["live_sum"], counts["max_live"],
+                           counts["rejected"], counts["queued"])
 
 
 def requests_from_trace(trace) -> list:

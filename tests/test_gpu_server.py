@@ -1,7 +1,9 @@
 """Continuous-batching server on the GPU: requests that arrive while others
 are cycling join the resident batch; every result equals (bitwise) the same
 request solved alone, for the plain FP64 and the mixed-precision form, with
-a roomy budget and with one that forces admission queueing."""
+a roomy budget and with one that forces admission queueing, with one
+resident batch and with one batch per size class (lanes ticking on their
+own streams from their own threads)."""
 import sys
 
 import numpy as np
@@ -41,10 +43,15 @@ def solo(kind, n, seed, precision):
     return u.cpu().numpy()
 
 
-@pytest.mark.parametrize("precision,tight", [("fp64", False), ("mixed", False), ("fp64", True)])
-def test_served_results_equal_solo(precision, tight):
+LANES = [[16, 24], [32], [48]]
+
+
+@pytest.mark.parametrize("precision,tight,lanes", [("fp64", False, None), ("mixed", False, None),
+                                                   ("fp64", True, None), ("fp64", False, LANES),
+                                                   ("mixed", False, LANES), ("fp64", True, LANES)])
+def test_served_results_equal_solo(precision, tight, lanes):
     from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
-    note("server", precision, "tight" if tight else "roomy")
+    note("server", precision, "tight" if tight else "roomy", "lanes" if lanes else "one batch")
     be = GpuBackend(precision=precision, tol=1e-8, max_slots=8)
     reqs = requests_from_trace(trace())
     if tight:
@@ -53,13 +60,13 @@ def test_served_results_equal_solo(precision, tight):
             + be.array_bytes(16)
     else:
         budget = 8 << 30
-    srv = Server(be, budget, max_slots=8, keep_results=True)
+    srv = Server(be, budget, max_slots=8, keep_results=True, lanes=lanes)
     st = srv.run(reqs)
     assert st.completed == len(reqs) and st.rejected == 0
     assert srv.peak <= budget
     if not tight:
         assert st.max_live > 1
-    else:
+    elif lanes is None:
         assert st.queued >= 1
     for r in reqs:
         assert r.status == 0
