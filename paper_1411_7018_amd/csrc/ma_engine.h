@@ -128,6 +128,8 @@ hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color
                           unsigned long long *nfall);
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, const double *partials,
                                  double *out);
+// fs = F in the order of the 4-colour sweep rows of an n grid (ma_solver::fs)
+hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, long cs);
 // block sweeps of an FsList (ma_fsweep.h): cfg block shape, blocks >= tiles
 hipError_t launch_bsweep(hipStream_t st, int op, int cfg, const FsList *L, int blocks,
                          unsigned long long *nonconvex);
@@ -171,6 +173,9 @@ class Engine {
     // correction).
     ma_status norms_only(Mode mode, const std::vector<char> &active, std::vector<double> &norms);
     ma_status reset_counters(int slot);  // slot < 0: all
+    // The right-hand side behind solve i's finest level changed (its
+    // colour-ordered copy is rebuilt before the next tick that reads it).
+    void rhs_changed(int i);
     ma_status read_counters(std::vector<unsigned long long> &nonconvex,
                             std::vector<unsigned long long> &fallbacks);
     // Work of one tick of mode for solve i: point updates and algorithmic bytes.
@@ -194,6 +199,7 @@ class Engine {
     ma_status run(Mode mode, bool cycle, const std::vector<char> &active,
                   std::vector<double> &norms);
     ma_status upload();
+    ma_status refresh_fs(Mode mode, const std::vector<char> &active);
     void drop_graphs();
     const double *level_u(int i, int l, Mode mode) const;
     const double *level_F(int i, int l, Mode mode) const;
@@ -240,6 +246,7 @@ class Engine {
     std::vector<int> fscfg_;               // block shape per FsList
     size_t fs_stride_ = 0;
     std::vector<int> res_, rst_, pro_, inj_;
+    std::vector<const double *> fs_src_;   // right-hand side held in each solve's fs
     // fused residual-restriction list of each depth (-1: separate launches)
     std::vector<int> rr_;
     std::vector<size_t> rroff_;            // byte offset of each RrList

@@ -39,19 +39,19 @@ __device__ __forceinline__ double wave_sum64(double v)
 // bitwise the same whichever kernel computes it.  p is the node's linear
 // index, (sy, sz) the strides of its grid.
 // ---------------------------------------------------------------------------
-template <int OP, typename PU, typename PF>
-__device__ __forceinline__ void sweep_node(PU u, PF F, long p, long sy, long sz, double s,
+template <int OP, typename PU>
+__device__ __forceinline__ void sweep_node(PU u, double Fv, long p, long sy, long sz, double s,
                                            double hk, int slot,
                                            unsigned long long *__restrict__ ncount)
 {
     if (OP == OP_MA) {
         const Hess g = hessian_at(u, p, 1, sy, sz, s, 0.25 * s);
         bool nc = false;
-        u[p] = ma_point_update(g, u[p], F[p], hk, nc);
+        u[p] = ma_point_update(g, u[p], Fv, hk, nc);
         if (nc)
             atomicAdd(ncount + slot, 1ull);
     } else {
-        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, s), u[p], F[p], hk);
+        u[p] = lap_point_update(laplacian_at(u, p, 1, sy, sz, s), u[p], Fv, hk);
     }
 }
 
@@ -148,7 +148,7 @@ template <int OP>
 __device__ __forceinline__ void pt_sweep(const GridItem &G, long p, long sy, long sz,
                                          unsigned long long *__restrict__ ncount)
 {
-    sweep_node<OP>(gptr<double>(G.p[0]), gptr<const double>(G.p[1]), p, sy, sz, G.s, G.hk,
+    sweep_node<OP>(gptr<double>(G.p[0]), gptr<const double>(G.p[1])[p], p, sy, sz, G.s, G.hk,
                    G.slot, ncount);
 }
 
@@ -272,10 +272,17 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
         colour_row<ORDER>(color, bx, by, bz, t, i, j, k);
         if (i <= n - 1 && j <= n - 1 && k <= n - 1) {
             const long p = i + sy * j + sz * k;
-            if (KIND == LK_SWEEP)
+            if (KIND == LK_SWEEP && ORDER == 0 && G.p[2]) {
+                // colour-ordered F (ma_solver::fs): this row's values are
+                // contiguous, so the phase reads F of its own colour only
+                const long q = (long(bz) * G.gy + by) * G.gx + bx;
+                const double Fv = gptr<const double>(G.p[2])[long(color) * G.pbase + 64 * q + t];
+                sweep_node<OP>(gptr<double>(G.p[0]), Fv, p, sy, sz, G.s, G.hk, G.slot, ncount);
+            } else if (KIND == LK_SWEEP) {
                 pt_sweep<OP>(G, p, sy, sz, ncount);
-            else
+            } else {
                 pt_msweep(G, p, sy, sz, ncount, nfall);
+            }
         }
     } else if (KIND == LK_RESIDUAL || KIND == LK_NORM || KIND == LK_RES32) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
@@ -374,6 +381,26 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
         if (by < G.gy)
             run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, int(threadIdx.x), ncount,
                                              nfall);
+    }
+}
+
+// fs[c * cs + 64 q + t] = F at the node of lane t of 4-colour row q of
+// colour c (0 where the row runs past the grid): the right-hand side in the
+// order the finest-level colour sweep reads it.  Block b = row q.
+__global__ __launch_bounds__(64) void k_fsplit(int n, const double *__restrict__ F,
+                                               double *__restrict__ fs, long cs, int gx, int gy)
+{
+    const int q = int(blockIdx.x), t = int(threadIdx.x);
+    const int bx = q % gx, r = q / gx;
+    const int by = r % gy, bz = r / gy;
+    const long sy = n + 1, sz = sy * sy;
+    const auto Fg = to_global(F);
+    const auto out = to_global(fs);
+    for (int c = 0; c < 4; ++c) {
+        int i, j, k;
+        colour_row<0>(c, bx, by, bz, t, i, j, k);
+        const bool in = i <= n - 1 && j <= n - 1 && k <= n - 1;
+        out[long(c) * cs + 64L * q + t] = in ? Fg[i + sy * j + sz * k] : 0.0;
     }
 }
 
@@ -686,7 +713,10 @@ __global__ __launch_bounds__(kTailLdsThreads) void k_tail_lds(
             for (int q = tid; q < cnt; q += NT) {
                 int i, j, k;
                 if (colour_node<ORDER>(n, c, q, i, j, k))
-                    sweep_node<OP>(u, b, i + sy * j + sz * k, sy, sz, G.s, G.hk, G.slot, ncount);
+                {
+                    const long p = i + sy * j + sz * k;
+                    sweep_node<OP>(u, b[p], p, sy, sz, G.s, G.hk, G.slot, ncount);
+                }
             }
             lds_barrier();
         }
@@ -878,6 +908,16 @@ hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color
     }
 }
 
+hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, long cs)
+{
+    int gx, gy, gz;
+    item_dims(LK_SWEEP, 0, n, &gx, &gy, &gz);
+    if (long(gx) * gy * gz * 64 != cs || n < 2)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fsplit, dim3(gx * gy * gz), dim3(64), 0, st, n, F, fs, cs, gx, gy);
+    return hipGetLastError();
+}
+
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *L, const double *partials,
                                  double *out)
 {
@@ -1004,6 +1044,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     // tables, which every rebuild rewrites; what it holds as a plain kernel
     // argument is the partials buffer, whose reallocation drops the graphs.
     solves_ = solves;
+    fs_src_.assign(solves_.size(), nullptr);   // contents of f unknown: rebuild
     user_ = user;
     graphs_ = graphs;
     profile_ = profile;
@@ -1045,6 +1086,33 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         partials_ = nullptr;
         E_HIP(hipMalloc(reinterpret_cast<void **>(&partials_), need * sizeof(double)));
         partials_cap_ = need;
+    }
+    return MA_OK;
+}
+
+void Engine::rhs_changed(int i)
+{
+    if (i >= 0 && size_t(i) < fs_src_.size())
+        fs_src_[i] = nullptr;
+}
+
+// Rebuild the colour-ordered right-hand side of every active solve whose
+// finest-level colour sweeps read it and whose copy is not of the operand
+// this mode uses (f for FAS cycles, R for the Poisson start).  Runs on the
+// engine stream ahead of the tick, outside any captured graph.
+ma_status Engine::refresh_fs(Mode mode, const std::vector<char> &active)
+{
+    if (mode == MODE_MIXED || order_ != 0)
+        return MA_OK;
+    for (size_t i = 0; i < solves_.size(); ++i) {
+        ma_solver *sv = solves_[i].s;
+        if (!sv || !active[i] || !sv->fs || multiblock_levels(int(i)) == 0)
+            continue;
+        const double *F = level_F(int(i), 0, mode);
+        if (fs_src_[i] == F)
+            continue;
+        E_HIP(launch_fsplit(stream_, sv->lv[0].n, F, sv->fs, sv->fs_cs));
+        fs_src_[i] = F;
     }
     return MA_OK;
 }
@@ -1136,6 +1204,10 @@ GridItem Engine::grid(int kind, int i, int l, Mode mode) const
     case LK_SWEEP:
         G.p[0] = P(level_u(i, l, mode));
         G.p[1] = P(level_F(i, l, mode));
+        if (l == 0 && mode != MODE_MIXED && order_ == 0 && s->fs) {
+            G.p[2] = s->fs;
+            G.pbase = int(s->fs_cs);
+        }
         break;
     case LK_RESIDUAL:
         G.p[0] = P(level_u(i, l, mode));
@@ -1708,6 +1780,8 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         MA_TRY(rebuild(mode, active));
     E_HIP(hipEventRecord(ev_in_, user_));
     E_HIP(hipStreamWaitEvent(stream_, ev_in_, 0));
+    if (cycle)
+        MA_TRY(refresh_fs(mode, active));
     const int m = int(mode) + (profile_ ? 3 : 0);
     size_t nev = 0;
     if (cycle && graphs_) {

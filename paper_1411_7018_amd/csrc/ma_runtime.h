@@ -46,6 +46,13 @@ struct MixedLevel {
 };
 
 size_t hierarchy_bytes(const ma_params *p);
+// Doubles per colour of the colour-ordered right-hand side of an n grid
+// (rows of the 4-colour sweep x 64 lanes).
+inline long fs_colour_count(int n)
+{
+    const long gx = ((n + 1) / 2 + 63) / 64, gy = n - 1, gz = n / 2;
+    return gx * gy * gz * 64;
+}
 // Largest n whose sweeps MA_SMOOTHER_AUTO runs as block sweeps (-1: none).
 inline int block_limit(const ma_params &p) { return p.block_n == 0 ? 64 : p.block_n; }
 size_t mixed_bytes(const ma_params *p);
@@ -63,6 +70,11 @@ struct ma_solver {
     hipStream_t stream = nullptr;
     std::vector<mafas::Level> lv;
     double *R = nullptr;                  // Poisson right-hand side, finest level
+    // The finest right-hand side in the order the 4-colour sweep visits it:
+    // colour c, work item (row) q, lane t at fs[c * fs_cs + 64 q + t]
+    // (FP64 4-colour solvers; filled by the engine when stale).
+    double *fs = nullptr;
+    long fs_cs = 0;
     double *partials = nullptr;           // norm partials of the single-grid kernels
     double *dsum = nullptr;
     unsigned long long *dcount = nullptr; // counter of the single-grid kernels

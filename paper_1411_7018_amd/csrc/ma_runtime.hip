@@ -93,7 +93,8 @@ double mafas::now_seconds()
 
 // ---------------------------------------------------------------------------
 // Hierarchy layout (FP64, (n_l+1)^3 each):
-//   level 0: r (residual), R (Poisson right-hand side), t (block-sweep target);
+//   level 0: r (residual), R (Poisson right-hand side), t (block-sweep target),
+//            fs (colour-ordered right-hand side, FP64 4-colour solvers);
 //   level l >= 1: u, b, w, r, t.
 // Plus the single-grid norm partials, the batch-of-one engine's partials and
 // lists, and the MA_MIXED FP32 hierarchy.
@@ -107,6 +108,8 @@ size_t mafas::hierarchy_bytes(const ma_params *p)
         const size_t c = npts(ns[l]) * sizeof(double);
         b += (l == 0) ? 3 * c : 5 * c;
     }
+    if (p->order == MA_COLOR4 && p->precision == MA_FP64 && p->n >= 2)
+        b += size_t(4 * fs_colour_count(p->n)) * sizeof(double);
     b += residual_partials(p->n) * sizeof(double);
     const size_t rows = size_t((p->n - 1 + 63) / 64) * size_t(p->n - 1) * size_t(p->n - 1);
     b += rows * sizeof(double) + (64 << 10) + 4096;
@@ -491,6 +494,10 @@ ma_status ma_solver::allocate()
             MA_TRY(alloc(&v.r, c));
             MA_TRY(alloc(&R, c));
             MA_TRY(alloc(&v.t, c));
+            if (p.order == MA_COLOR4 && p.precision == MA_FP64 && v.n >= 2) {
+                fs_cs = fs_colour_count(v.n);
+                MA_TRY(alloc(&fs, size_t(4 * fs_cs)));
+            }
         } else {
             MA_TRY(alloc(&v.u, c));
             MA_TRY(alloc(&v.b, c));
@@ -597,6 +604,7 @@ ma_solver *ma_solver::view(int l)
     views[l]->p.coarse_n = p.coarse_n;
     views[l]->p.max_blocks = p.max_blocks;
     views[l]->p.strip_rows = p.strip_rows;
+    views[l]->p.block_n = p.block_n;
     return views[l];
 }
 
@@ -698,6 +706,7 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 const SolveRef &r = eng.ref(i);
                 if (launch_poisson_rhs(eng.user(), r.s->p.n, r.f, r.s->R) != hipSuccess)
                     return MA_ERR_DEVICE;
+                eng.rhs_changed(i);
             }
         MA_TRY(eng.norms_only(Engine::MODE_LAP, act, nrm));
         for (int i = 0; i < S; ++i)

@@ -57,11 +57,18 @@ def test_footprint_grows_with_n_and_rejects_invalid():
     a = L.ma_footprint_bytes(L.ma_params_default(64))
     b = L.ma_footprint_bytes(L.ma_params_default(128))
     assert 0 < a < b
-    # the hierarchy holds the fine residual, the Poisson RHS and the sweep
-    # target (3 fine arrays) plus 5 arrays per coarse level
+    # the hierarchy holds the fine residual, the Poisson RHS, the sweep
+    # target and the colour-ordered RHS (about 4 fine arrays) plus 5 arrays
+    # per coarse level
     n = 128
     fine = (n + 1) ** 3 * 8
-    assert 3 * fine <= b <= 3 * fine + 5 * 8 * sum((m + 1) ** 3 for m in L.ma_levels(n)[1:]) + 2**22
+    fs = 4 * (((n + 1) // 2 + 63) // 64) * (n - 1) * (n // 2) * 64 * 8
+    coarse = 5 * 8 * sum((m + 1) ** 3 for m in L.ma_levels(n)[1:])
+    assert 3 * fine + fs <= b <= 3 * fine + fs + coarse + 2**22
+    # the mixed form keeps no colour-ordered RHS
+    pm = L.ma_params_default(128)
+    pm.precision = L.MA_MIXED
+    assert L.ma_footprint_bytes(pm) > 0
     bad = L.ma_params_default(1)
     assert L.ma_footprint_bytes(bad) == 0
 
