@@ -256,7 +256,7 @@ class Engine {
 
     double *partials_ = nullptr;
     size_t partials_cap_ = 0;
-    double *dnorm_ = nullptr, *hnorm_ = nullptr;
+    double *dnorm_ = nullptr, *hnorm_ = nullptr;   // dnorm_: device alias of the pinned hnorm_
     unsigned long long *dcount_ = nullptr, *dfall_ = nullptr, *hcount_ = nullptr;
 
     Mode built_mode_ = MODE_MA;

@@ -983,7 +983,6 @@ Engine::~Engine()
     }
     (void)hipFree(dl_);
     (void)hipFree(partials_);
-    (void)hipFree(dnorm_);
     (void)hipFree(dcount_);
     (void)hipFree(dfall_);
     if (hstage_)
@@ -1065,10 +1064,14 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     if (!stream_) {
         E_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
         E_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
-        E_HIP(hipMalloc(reinterpret_cast<void **>(&dnorm_), kMaxGrids * sizeof(double)));
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dcount_), kMaxGrids * sizeof(unsigned long long)));
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dfall_), kMaxGrids * sizeof(unsigned long long)));
-        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_), kMaxGrids * sizeof(double)));
+        // The reduction kernel writes each tick's sums straight into this
+        // pinned, coherent host buffer: no copy is queued after a tick, and
+        // the host reads it once the stream has drained.
+        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_), kMaxGrids * sizeof(double),
+                            hipHostMallocMapped | hipHostMallocCoherent));
+        E_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dnorm_), hnorm_, 0));
         E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hcount_),
                             2 * kMaxGrids * sizeof(unsigned long long)));
     }
@@ -1806,8 +1809,6 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         MA_TRY(enqueue(mode, cycle));
         nev = pev_used_;
     }
-    E_HIP(hipMemcpyAsync(hnorm_, dnorm_, solves_.size() * sizeof(double), hipMemcpyDeviceToHost,
-                         stream_));
     E_HIP(hipStreamSynchronize(stream_));
     norms.resize(solves_.size());
     for (size_t i = 0; i < solves_.size(); ++i)
