@@ -93,7 +93,7 @@ ma_status ma_solve_batch(ma_solver *const *solvers, double *const *u, const doub
                 live |= x.phase != SolveState::DONE;
             if (!live)
                 break;
-            if (drive_step(eng, ptr) != MA_OK)
+            if (drive_step(eng, ptr, false, true) != MA_OK)
                 return s0->fail(MA_ERR_DEVICE, eng.error());
         }
         std::vector<unsigned long long> nc, fb;

@@ -13,6 +13,8 @@
 #include "ma_fsweep.h"
 #include "ma_runtime.h"
 
+#include <cstddef>
+#include <deque>
 #include <vector>
 
 namespace mafas {
@@ -51,13 +53,19 @@ inline int padded_items(int gx, int gy, int gz, int w)
 
 // Lists live in one device buffer at a fixed stride of list_bytes(slots):
 // the header followed by ngrids descriptors (g[] below is only the bound).
+// stopped (every list header, at byte 8): bit s set when solve s has met its
+// stopping test.  Work of such a solve is skipped, so a tick queued before
+// the host has read the previous tick's norm does nothing for a solve that
+// has stopped.  The mask sits beside ngrids and total, so a kernel reads it
+// with the header it loads anyway.
 struct BatchList {
     int ngrids;
     int total;     // work items over all grids
-    int pad[2];
+    unsigned long long stopped;
     GridItem g[kMaxGrids];
 };
 constexpr size_t list_bytes(int ngrids) { return 16 + sizeof(GridItem) * size_t(ngrids); }
+static_assert(offsetof(BatchList, g) == 16, "list header is 16 bytes");
 
 // The coarse levels of one solve: per level the descriptors of its sweep,
 // residual, restriction (to the next level) and prolongation (from it).
@@ -73,16 +81,17 @@ struct RrGrid {
     int n;
     int tiles_x, tiles_y, tiles_z;
     int start;      // first tile of this grid in the launch
-    int pad;
+    int slot;       // solve index
     double s;       // 1/h^2 of the fine grid
 };
 struct RrList {
     int ngrids;
     int total;
-    int pad[2];
+    unsigned long long stopped;
     RrGrid g[kMaxGrids];
 };
 constexpr size_t rr_list_bytes(int ngrids) { return 16 + sizeof(RrGrid) * size_t(ngrids); }
+static_assert(offsetof(RrList, g) == 16, "list header is 16 bytes");
 
 // LDS form: offsets (in doubles) of each level's u, b, w, r in LDS, -1
 // where the level has no such array (w above the first level, r on the
@@ -99,10 +108,12 @@ struct TailEntry {
 };
 struct TailList {
     int nsolves;
-    int pad[3];
+    int pad;
+    unsigned long long stopped;
     TailEntry e[kMaxGrids];
 };
 constexpr size_t tail_bytes(int nsolves) { return 16 + sizeof(TailEntry) * size_t(nsolves); }
+static_assert(offsetof(TailList, e) == 16, "list header is 16 bytes");
 
 enum ListKind {
     LK_SWEEP,      // p: u, F                        items: rows of one colour
@@ -126,8 +137,34 @@ void item_dims(int kind, int order, int n, int *gx, int *gy, int *gz);
 hipError_t launch_batched(hipStream_t st, int kind, int op, int order, int color, int rmode,
                           const BatchList *dlist, int blocks, unsigned long long *ncount,
                           unsigned long long *nfall);
+// Where the norm reduction puts each solve's sum of squares (see
+// k_batched_reduce): sum and stamp are pinned host rings of 2 * kMaxGrids
+// entries (device aliases), seq and thr per-slot device arrays.  base is the
+// device list table and stop points into it: stop[0] list headers follow,
+// as byte offsets from base, whose stopped masks a stopping solve sets.
+struct NormRing {
+    double *sum;
+    unsigned *stamp;
+    unsigned *seq;
+    const double *thr;
+    char *base;
+    const unsigned *stop;
+};
+// Thresholds to arm (k_arm), at most kMaxGrids per launch.
+struct ArmSet {
+    int count;
+    int slot[kMaxGrids];
+    double thr[kMaxGrids];
+};
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, const double *partials,
-                                 double *out);
+                                 const NormRing &ring);
+// base, stop: the list table and its header offsets as in NormRing, or null
+// before any list exists.
+hipError_t launch_arm(hipStream_t st, const ArmSet &a, double *thr, char *base,
+                      const unsigned *stop);
+// Largest sum of squares x >= 0 of an n grid whose norm sqrt(x / n^3), as
+// the engine computes it, is at most c (-1 when c is negative or NaN).
+double sum_threshold(double c, int n);
 // fs = F in the order of the 4-colour sweep rows of an n grid (ma_solver::fs)
 hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, long cs);
 // block sweeps of an FsList (ma_fsweep.h): cfg block shape, blocks >= tiles
@@ -167,11 +204,28 @@ class Engine {
     ma_status set(const std::vector<SolveRef> &solves, hipStream_t user, bool graphs,
                   bool profile);
     // One V-cycle (MA, LAP) or one outer correction (MIXED) of every active
-    // solve, then its discrete L2 residual norm into norms[i].
+    // solve, then its discrete L2 residual norm into norms[i].  The solves
+    // run unconditionally (their stopping thresholds are disarmed).
     ma_status tick(Mode mode, const std::vector<char> &active, std::vector<double> &norms);
     // The residual norms alone (MIXED: also stores r64 in FP32 for the next
     // correction).
     ma_status norms_only(Mode mode, const std::vector<char> &active, std::vector<double> &norms);
+    // A tick for the cycle driver.  thr[i] arms solve i's stopping threshold
+    // on its sum of squares (sum_threshold; negative: none): the tick that
+    // meets it sets the solve's device halt flag.  ahead: queue one more tick
+    // of the same solves before waiting for this one, so the GPU does not
+    // idle while the host reads the norms; a later tick_ahead call with
+    // these solves consumes it, and a solve that stopped skips it on the
+    // device.  The caller queues ahead only while no solve can stop for a
+    // reason the device does not see (a cycle limit).
+    ma_status tick_ahead(Mode mode, const std::vector<char> &active, const std::vector<double> &thr,
+                         bool ahead, std::vector<double> &norms);
+    // Wait for ticks still queued ahead (each solve in them must have stopped).
+    ma_status settle();
+    // Ticks queued and not yet read.
+    int pending() const { return int(fifo_.size()); }
+    // The device halt flag of solve i as last seen by the host.
+    bool halted(int i) const { return halted_[i] != 0; }
     ma_status reset_counters(int slot);  // slot < 0: all
     // The right-hand side behind solve i's finest level changed (its
     // colour-ordered copy is rebuilt before the next tick that reads it).
@@ -188,16 +242,21 @@ class Engine {
     hipStream_t user() const { return user_; }
     bool mixed() const { return mixed_; }
 
-  private:
     ma_status fail(ma_status st, const std::string &m)
     {
         err_ = m;
         return st;
     }
+
+  private:
     ma_status rebuild(Mode mode, const std::vector<char> &active);
     ma_status enqueue(Mode mode, bool cycle);
-    ma_status run(Mode mode, bool cycle, const std::vector<char> &active,
-                  std::vector<double> &norms);
+    ma_status launch(Mode mode, bool cycle, const std::vector<char> &active);
+    ma_status collect(std::vector<double> &norms);
+    ma_status plain(Mode mode, bool cycle, const std::vector<char> &active,
+                    std::vector<double> &norms);
+    void arm(int slot, double thr);
+    ma_status flush_arms();
     ma_status upload();
     ma_status refresh_fs(Mode mode, const std::vector<char> &active);
     void drop_graphs();
@@ -256,7 +315,31 @@ class Engine {
 
     double *partials_ = nullptr;
     size_t partials_cap_ = 0;
-    double *dnorm_ = nullptr, *hnorm_ = nullptr;   // dnorm_: device alias of the pinned hnorm_
+    // Norm ring (k_batched_reduce): hnorm_ / hstamp_ pinned coherent host
+    // memory, 2 * kMaxGrids entries each, dnorm_ / dstamp_ their device
+    // aliases; dseq_, dthr_ per-slot device state.
+    double *dnorm_ = nullptr, *hnorm_ = nullptr;
+    unsigned *dstamp_ = nullptr, *hstamp_ = nullptr, *dseq_ = nullptr;
+    double *dthr_ = nullptr;
+    size_t stoff_ = 0;   // byte offset of the header-offset table in the lists
+    // host view of the device state: sums consumed per slot, armed
+    // thresholds and halt flags, and thresholds queued for the next launch
+    std::vector<unsigned> seq_ = std::vector<unsigned>(kMaxGrids, 0u);
+    std::vector<double> thr_dev_ = std::vector<double>(kMaxGrids, -1.0);
+    std::vector<char> halted_ = std::vector<char>(kMaxGrids, 0);
+    std::vector<char> armq_ = std::vector<char>(kMaxGrids, 0);
+    std::vector<double> armv_ = std::vector<double>(kMaxGrids, -1.0);
+    // queued ticks, oldest first, and spare events
+    struct Pending {
+        Mode mode;
+        bool cycle;
+        std::vector<char> active;
+        hipEvent_t ev;
+        size_t nev;  // profile events recorded by the tick
+    };
+    std::deque<Pending> fifo_;
+    std::vector<hipEvent_t> evpool_;
+    hipStream_t side_ = nullptr;  // counter reads while a skipped tick is queued
     unsigned long long *dcount_ = nullptr, *dfall_ = nullptr, *hcount_ = nullptr;
 
     Mode built_mode_ = MODE_MA;

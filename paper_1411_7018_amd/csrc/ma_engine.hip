@@ -20,7 +20,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
+#include <limits>
 
 namespace mafas {
 
@@ -367,10 +369,13 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
             g1 = mid - 1;
     }
     int g = g0;
+    const unsigned long long stopped = L->stopped;
     for (; it < hi; it += bpx) {
         while (g + 1 < ng && L->g[g + 1].start <= it)
             ++g;
         const GridItem &G = L->g[g];
+        if ((stopped >> G.slot) & 1ull)
+            continue;
         const int local = it - G.start;
         const int bx = local % G.gx;
         int rest = local / G.gx;
@@ -406,16 +411,24 @@ __global__ __launch_bounds__(64) void k_fsplit(int n, const double *__restrict__
 
 // Fixed-order per-grid sum of the partials of a norm list: thread t adds
 // partials t, t + 1024, ... in order, then a fixed shuffle tree per wave and
-// the 16 wave sums in order.
+// the 16 wave sums in order.  The sum of solve `slot` goes to the pinned
+// host ring R: the k-th sum of a slot (k = R.seq[slot], counted on the
+// device) lands in entry k & 1 with its k stamped beside it.  When the
+// slot's threshold is armed (thr >= 0), a sum at or below it, or one that is
+// not finite, means the host's stopping test has passed: the slot's bit is
+// set in the stopped mask of every list header, and the ticks already
+// queued after this one skip the solve.
 __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__restrict__ L,
                                                          const double *__restrict__ partials,
-                                                         double *__restrict__ out)
+                                                         NormRing R)
 {
     __shared__ double part[16];
     const int g = blockIdx.x;
     if (g >= L->ngrids)
         return;
     const GridItem &G = L->g[g];
+    if ((L->stopped >> G.slot) & 1ull)
+        return;
     const int cnt = G.gx * G.gy * G.gz;
     double v = 0.0;
     for (int q = threadIdx.x; q < cnt; q += 1024)
@@ -428,7 +441,36 @@ __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__rest
         double s = 0.0;
         for (int w = 0; w < 16; ++w)
             s += part[w];
-        out[G.slot] = s;
+        const int slot = G.slot;
+        const unsigned k = R.seq[slot];
+        const int e = int(k & 1u) * kMaxGrids + slot;
+        R.sum[e] = s;
+        R.stamp[e] = k;
+        R.seq[slot] = k + 1u;
+        const double t = R.thr[slot];
+        if (t >= 0.0 && (s <= t || !isfinite(s))) {
+            const unsigned nh = R.stop[0];
+            for (unsigned q = 0; q < nh; ++q)
+                atomicOr(reinterpret_cast<unsigned long long *>(R.base + R.stop[1 + q] + 8),
+                         1ull << slot);
+        }
+    }
+}
+
+// Arm solves for pipelined ticks: slot a.slot[q] takes threshold a.thr[q]
+// (negative: never stop) and its bit cleared in every list header.
+__global__ __launch_bounds__(64) void k_arm(ArmSet a, double *__restrict__ thr, char *base,
+                                            const unsigned *__restrict__ stop)
+{
+    const int q = int(threadIdx.x);
+    if (q < a.count) {
+        thr[a.slot[q]] = a.thr[q];
+        if (stop) {
+            const unsigned nh = stop[0];
+            for (unsigned h = 0; h < nh; ++h)
+                atomicAnd(reinterpret_cast<unsigned long long *>(base + stop[1 + h] + 8),
+                          ~(1ull << a.slot[q]));
+        }
     }
 }
 
@@ -544,6 +586,8 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailList *__restric
     if (int(blockIdx.x) >= T->nsolves)
         return;
     const TailEntry &E = T->e[blockIdx.x];
+    if ((T->stopped >> E.lv[0].sw.slot) & 1ull)
+        return;
     const int L = E.nlev;
     constexpr int colours = ORDER == 0 ? 4 : 8;
     for (int l = 0; l < L; ++l) {
@@ -601,6 +645,8 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
     while (g + 1 < ng && Lst->g[g + 1].start <= t)
         ++g;
     const RrGrid &G = Lst->g[g];
+    if ((Lst->stopped >> G.slot) & 1ull)
+        return;
     const int tile = t - G.start;
     const int nf = G.n, nc = nf / 2;
     const int tx = tile % G.tiles_x, rest = tile / G.tiles_x;
@@ -686,6 +732,8 @@ __global__ __launch_bounds__(kTailLdsThreads) void k_tail_lds(
     if (int(blockIdx.x) >= T->nsolves)
         return;
     const TailEntry &E = T->e[blockIdx.x];
+    if ((T->stopped >> E.lv[0].sw.slot) & 1ull)
+        return;
     const int L = E.nlev;
     const int tid = int(threadIdx.x);
     constexpr int NT = kTailLdsThreads;
@@ -919,9 +967,21 @@ hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, lon
 }
 
 hipError_t launch_batched_reduce(hipStream_t st, const BatchList *L, const double *partials,
-                                 double *out)
+                                 const NormRing &ring)
 {
-    hipLaunchKernelGGL(k_batched_reduce, dim3(kMaxGrids), dim3(1024), 0, st, L, partials, out);
+    hipLaunchKernelGGL(k_batched_reduce, dim3(kMaxGrids), dim3(1024), 0, st, L, partials, ring);
+    return hipGetLastError();
+}
+
+hipError_t launch_arm(hipStream_t st, const ArmSet &a, double *thr, char *base,
+                      const unsigned *stop)
+{
+    if (a.count < 0 || a.count > kMaxGrids || (!base) != (!stop))
+        return hipErrorInvalidValue;
+    for (int q = 0; q < a.count; ++q)
+        if (a.slot[q] < 0 || a.slot[q] >= kMaxGrids)
+            return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, st, a, thr, base, stop);
     return hipGetLastError();
 }
 
@@ -972,23 +1032,36 @@ hipError_t launch_tail_lds(hipStream_t st, int mode, int order, int rmode, const
 // ---------------------------------------------------------------------------
 Engine::~Engine()
 {
+    // ticks queued ahead may still run: drain the stream before freeing
+    if (stream_)
+        (void)hipStreamSynchronize(stream_);
     drop_graphs();
     for (hipEvent_t e : pev_)
         (void)hipEventDestroy(e);
+    for (const Pending &p : fifo_)
+        (void)hipEventDestroy(p.ev);
+    for (hipEvent_t e : evpool_)
+        (void)hipEventDestroy(e);
     if (ev_in_)
         (void)hipEventDestroy(ev_in_);
-    if (stream_) {
-        (void)hipStreamSynchronize(stream_);
+    if (stream_)
         (void)hipStreamDestroy(stream_);
+    if (side_) {
+        (void)hipStreamSynchronize(side_);
+        (void)hipStreamDestroy(side_);
     }
     (void)hipFree(dl_);
     (void)hipFree(partials_);
     (void)hipFree(dcount_);
     (void)hipFree(dfall_);
+    (void)hipFree(dseq_);
+    (void)hipFree(dthr_);
     if (hstage_)
         (void)hipHostFree(hstage_);
     if (hnorm_)
         (void)hipHostFree(hnorm_);
+    if (hstamp_)
+        (void)hipHostFree(hstamp_);
     if (hcount_)
         (void)hipHostFree(hcount_);
 }
@@ -1039,6 +1112,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
+    MA_TRY(settle());
     // A captured tick reads the grids' operand pointers from the device
     // tables, which every rebuild rewrites; what it holds as a plain kernel
     // argument is the partials buffer, whose reallocation drops the graphs.
@@ -1066,12 +1140,28 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         E_HIP(hipEventCreateWithFlags(&ev_in_, hipEventDisableTiming));
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dcount_), kMaxGrids * sizeof(unsigned long long)));
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dfall_), kMaxGrids * sizeof(unsigned long long)));
-        // The reduction kernel writes each tick's sums straight into this
-        // pinned, coherent host buffer: no copy is queued after a tick, and
-        // the host reads it once the stream has drained.
-        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_), kMaxGrids * sizeof(double),
+        E_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+        // The reduction kernel writes each tick's sums straight into these
+        // pinned, coherent host buffers: no copy is queued after a tick, and
+        // the host reads them once the tick's event has completed.
+        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_), 2 * kMaxGrids * sizeof(double),
                             hipHostMallocMapped | hipHostMallocCoherent));
         E_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dnorm_), hnorm_, 0));
+        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstamp_), 2 * kMaxGrids * sizeof(unsigned),
+                            hipHostMallocMapped | hipHostMallocCoherent));
+        E_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dstamp_), hstamp_, 0));
+        for (int e = 0; e < 2 * kMaxGrids; ++e)
+            hstamp_[e] = ~0u;
+        E_HIP(hipMalloc(reinterpret_cast<void **>(&dseq_), kMaxGrids * sizeof(unsigned)));
+        E_HIP(hipMalloc(reinterpret_cast<void **>(&dthr_), kMaxGrids * sizeof(double)));
+        E_HIP(hipMemsetAsync(dseq_, 0, kMaxGrids * sizeof(unsigned), stream_));
+        ArmSet a;
+        a.count = kMaxGrids;
+        for (int i = 0; i < kMaxGrids; ++i) {
+            a.slot[i] = i;
+            a.thr[i] = -1.0;
+        }
+        E_HIP(launch_arm(stream_, a, dthr_, nullptr, nullptr));
         E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hcount_),
                             2 * kMaxGrids * sizeof(unsigned long long)));
     }
@@ -1122,6 +1212,7 @@ ma_status Engine::refresh_fs(Mode mode, const std::vector<char> &active)
 
 ma_status Engine::reset_counters(int slot)
 {
+    MA_TRY(settle());
     if (slot < 0) {
         E_HIP(launch_fill_u64(stream_, kMaxGrids, 0ull, dcount_));
         E_HIP(launch_fill_u64(stream_, kMaxGrids, 0ull, dfall_));
@@ -1135,11 +1226,23 @@ ma_status Engine::reset_counters(int slot)
 ma_status Engine::read_counters(std::vector<unsigned long long> &nonconvex,
                                 std::vector<unsigned long long> &fallbacks)
 {
+    // With ticks queued ahead still on the engine stream, every solve in them
+    // has stopped, so they leave the counters alone: read them on the side
+    // stream instead of waiting for those ticks.  Everything queued before
+    // them has completed (the host waited for the last tick it consumed).
+    hipStream_t st = stream_;
+    if (!fifo_.empty()) {
+        for (const Pending &p : fifo_)
+            for (size_t i = 0; i < solves_.size(); ++i)
+                if (solves_[i].s && p.active[i] && !halted_[i])
+                    return fail(MA_ERR_DEVICE, "internal: counters read with a live tick queued");
+        st = side_;
+    }
     E_HIP(hipMemcpyAsync(hcount_, dcount_, kMaxGrids * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, stream_));
+                         hipMemcpyDeviceToHost, st));
     E_HIP(hipMemcpyAsync(hcount_ + kMaxGrids, dfall_, kMaxGrids * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, stream_));
-    E_HIP(hipStreamSynchronize(stream_));
+                         hipMemcpyDeviceToHost, st));
+    E_HIP(hipStreamSynchronize(st));
     nonconvex.assign(hcount_, hcount_ + solves_.size());
     fallbacks.assign(hcount_ + kMaxGrids, hcount_ + kMaxGrids + solves_.size());
     return MA_OK;
@@ -1310,7 +1413,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         BatchList L;
         L.ngrids = 0;
         L.total = 0;
-        L.pad[0] = L.pad[1] = 0;
+        L.stopped = 0;
         int start = 0;
         long bound = 0;
         for (int i = 0; i < S; ++i) {
@@ -1453,6 +1556,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             }
         }
         T->nsolves = nt;
+        T->stopped = 0;
         tail_blocks_ = bound;
     }
 
@@ -1496,7 +1600,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                     for (int half = 0; half < 2; ++half) {
                         FsList L;
                         L.ngrids = 0;
-                        L.pad[0] = L.pad[1] = 0;
+                        L.stopped = 0;
                         int start = 0;
                         long bound = 0;
                         for (int i = 0; i < S; ++i) {
@@ -1544,7 +1648,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         for (int d = 0; d < D_; ++d) {
             RrList Lr;
             Lr.ngrids = 0;
-            Lr.pad[0] = Lr.pad[1] = 0;
+            Lr.stopped = 0;
             int start = 0;
             long bound = 0;
             for (int i = 0; i < S; ++i) {
@@ -1559,6 +1663,7 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                 G.uc = sv->lv[d + 1].u;
                 G.bc = sv->lv[d + 1].b;
                 G.n = sv->lv[d].n;
+                G.slot = i;
                 const int tc = (G.n / 2 + 1 + kRrTile - 1) / kRrTile;
                 G.tiles_x = G.tiles_y = G.tiles_z = tc;
                 G.s = double(G.n) * double(G.n);
@@ -1579,6 +1684,21 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             hbuf_.resize(off + rr_stride_, 0);
             std::memcpy(hbuf_.data() + off, &Lr, rr_list_bytes(Lr.ngrids));
         }
+    }
+
+    // Byte offsets of every list header (count first): a solve that stops
+    // sets its bit in each header's stopped mask (k_batched_reduce), arming
+    // clears it (k_arm).  The upload writes every mask as zero.
+    {
+        std::vector<unsigned> offs(loff_.begin(), loff_.end());
+        offs.push_back(unsigned(toff_));
+        offs.insert(offs.end(), fsoff_.begin(), fsoff_.end());
+        offs.insert(offs.end(), rroff_.begin(), rroff_.end());
+        const unsigned cnt = unsigned(offs.size());
+        stoff_ = (hbuf_.size() + 15) / 16 * 16;
+        hbuf_.resize(stoff_ + sizeof(unsigned) * (1 + offs.size()), 0);
+        std::memcpy(hbuf_.data() + stoff_, &cnt, sizeof(cnt));
+        std::memcpy(hbuf_.data() + stoff_ + sizeof(cnt), offs.data(), sizeof(unsigned) * cnt);
     }
 
     prof_bytes_tick_ = 0.0;
@@ -1745,7 +1865,9 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
         }
     }
     MA_TRY(go(mixed ? LK_RES32 : LK_NORM, norm_, 0));
-    E_HIP(launch_batched_reduce(stream_, L(norm_), partials_, dnorm_));
+    E_HIP(launch_batched_reduce(stream_, L(norm_), partials_,
+                                NormRing{dnorm_, dstamp_, dseq_, dthr_, dl_,
+                                         reinterpret_cast<const unsigned *>(dl_ + stoff_)}));
     return MA_OK;
 }
 
@@ -1771,16 +1893,22 @@ std::vector<int> Engine::shape() const
     s.push_back(int(rroff_.size()));
     s.push_back(rroff_.empty() ? 0 : int(rroff_[0]));
     s.insert(s.end(), rrblocks_.begin(), rrblocks_.end());
+    s.push_back(int(stoff_));
     return s;
 }
 
-ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
-                      std::vector<double> &norms)
+// Queue one tick (cycle) or one norm evaluation of the active solves on the
+// engine stream, followed by an event; the host waits in collect().
+ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
 {
     if (active.size() != solves_.size())
         return fail(MA_ERR_ARG, "active mask size");
-    if (!built_ || mode != built_mode_ || active != built_active_)
+    if (!built_ || mode != built_mode_ || active != built_active_) {
+        if (!fifo_.empty())
+            return fail(MA_ERR_DEVICE, "internal: list rebuild with ticks in flight");
         MA_TRY(rebuild(mode, active));
+    }
+    MA_TRY(flush_arms());
     E_HIP(hipEventRecord(ev_in_, user_));
     E_HIP(hipStreamWaitEvent(stream_, ev_in_, 0));
     if (cycle)
@@ -1809,16 +1937,56 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         MA_TRY(enqueue(mode, cycle));
         nev = pev_used_;
     }
-    E_HIP(hipStreamSynchronize(stream_));
+    hipEvent_t ev = nullptr;
+    if (!evpool_.empty()) {
+        ev = evpool_.back();
+        evpool_.pop_back();
+    } else {
+        E_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    const hipError_t er = hipEventRecord(ev, stream_);
+    if (er != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        return fail(MA_ERR_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(er));
+    }
+    fifo_.push_back(Pending{mode, cycle, active, ev, nev});
+    return MA_OK;
+}
+
+// Wait for the oldest queued tick and read the norms of the solves it ran
+// (those not halted before it).  The sum of a slot is the next entry of its
+// ring; a stamp that disagrees with the host's count means the host and the
+// device disagree on which ticks ran, and fails.
+ma_status Engine::collect(std::vector<double> &norms)
+{
+    if (fifo_.empty())
+        return fail(MA_ERR_DEVICE, "internal: no tick to collect");
+    Pending p = std::move(fifo_.front());
+    fifo_.pop_front();
+    const hipError_t er = hipEventSynchronize(p.ev);
+    evpool_.push_back(p.ev);
+    if (er != hipSuccess)
+        return fail(MA_ERR_DEVICE, std::string("tick: ") + hipGetErrorString(er));
     norms.resize(solves_.size());
-    for (size_t i = 0; i < solves_.size(); ++i)
-        if (solves_[i].s && active[i]) {
-            const int n = solves_[i].s->p.n;
-            const double h = 1.0 / double(n);
-            norms[i] = std::sqrt(hnorm_[i] * h * h * h);
-        }
-    if (profile_ && cycle) {
-        for (size_t q = 0; q + 1 < nev; q += 2) {
+    for (size_t i = 0; i < solves_.size(); ++i) {
+        if (!solves_[i].s || !p.active[i] || halted_[i])
+            continue;
+        const unsigned k = seq_[i];
+        const size_t e = size_t(k & 1u) * kMaxGrids + i;
+        if (hstamp_[e] != k)
+            return fail(MA_ERR_DEVICE, "internal: norm ring out of step with the host");
+        const double raw = hnorm_[e];
+        seq_[i] = k + 1u;
+        const int n = solves_[i].s->p.n;
+        const double h = 1.0 / double(n);
+        norms[i] = std::sqrt(raw * h * h * h);
+        // the device's decision in k_batched_reduce, on the same values
+        const double t = thr_dev_[i];
+        if (t >= 0.0 && (raw <= t || !std::isfinite(raw)))
+            halted_[i] = 1;
+    }
+    if (profile_ && p.cycle) {
+        for (size_t q = 0; q + 1 < p.nev; q += 2) {
             float ms = 0.f;
             E_HIP(hipEventElapsedTime(&ms, pev_[q], pev_[q + 1]));
             prof_seconds_ += 1e-3 * double(ms);
@@ -1827,6 +1995,136 @@ ma_status Engine::run(Mode mode, bool cycle, const std::vector<char> &active,
         prof_launches_ += prof_launches_tick_;
     }
     return MA_OK;
+}
+
+// Wait for every tick still queued.  Such ticks were queued ahead of the
+// host's stopping test; each solve in them must have stopped before them
+// (the device skipped it), else the host would lose a cycle it ran.
+ma_status Engine::settle()
+{
+    while (!fifo_.empty()) {
+        Pending p = std::move(fifo_.front());
+        fifo_.pop_front();
+        const hipError_t er = hipEventSynchronize(p.ev);
+        evpool_.push_back(p.ev);
+        if (er != hipSuccess)
+            return fail(MA_ERR_DEVICE, std::string("tick: ") + hipGetErrorString(er));
+        for (size_t i = 0; i < solves_.size(); ++i)
+            if (solves_[i].s && p.active[i] && !halted_[i])
+                return fail(MA_ERR_DEVICE,
+                            "internal: a tick queued ahead ran for a solve that had not stopped");
+    }
+    return MA_OK;
+}
+
+// Largest non-negative sum of squares x for which the host's stopping test
+// sqrt(x h h h) <= c passes (h = 1/n, the expression collect() evaluates);
+// the test is monotone in x, so it passes exactly for x <= the result.
+// Bisection over the ordered bit patterns of the non-negative doubles.
+double sum_threshold(double c, int n)
+{
+    if (!(c >= 0.0) || n < 1)
+        return -1.0;
+    const double h = 1.0 / double(n);
+    auto ok = [&](double x) { return std::sqrt(x * h * h * h) <= c; };
+    auto val = [](uint64_t b) {
+        double x;
+        std::memcpy(&x, &b, sizeof(x));
+        return x;
+    };
+    const double top = std::numeric_limits<double>::max();
+    if (ok(top))
+        return top;
+    uint64_t lo = 0, hi;   // ok(val(lo)) holds, ok(val(hi)) does not
+    std::memcpy(&hi, &top, sizeof(hi));
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (ok(val(mid)))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return val(lo);
+}
+
+// Queue (slot, thr) for the next launch unless the device already holds
+// that threshold with a clear halt flag.
+void Engine::arm(int slot, double thr)
+{
+    if (thr_dev_[slot] == thr && !halted_[slot] && !armq_[slot])
+        return;
+    armq_[slot] = 1;
+    armv_[slot] = thr;
+}
+
+ma_status Engine::flush_arms()
+{
+    ArmSet a;
+    a.count = 0;
+    for (int i = 0; i < kMaxGrids; ++i)
+        if (armq_[i]) {
+            a.slot[a.count] = i;
+            a.thr[a.count] = armv_[i];
+            ++a.count;
+        }
+    if (a.count == 0)
+        return MA_OK;
+    if (!fifo_.empty())
+        return fail(MA_ERR_DEVICE, "internal: thresholds changed with ticks in flight");
+    E_HIP(launch_arm(stream_, a, dthr_, dl_,
+                     dl_ ? reinterpret_cast<const unsigned *>(dl_ + stoff_) : nullptr));
+    for (int q = 0; q < a.count; ++q) {
+        const int i = a.slot[q];
+        thr_dev_[i] = armv_[i];
+        halted_[i] = 0;
+        armq_[i] = 0;
+    }
+    return MA_OK;
+}
+
+ma_status Engine::plain(Mode mode, bool cycle, const std::vector<char> &active,
+                        std::vector<double> &norms)
+{
+    if (active.size() != solves_.size())
+        return fail(MA_ERR_ARG, "active mask size");
+    MA_TRY(settle());
+    for (size_t i = 0; i < active.size(); ++i)
+        if (active[i])
+            arm(int(i), -1.0);
+    MA_TRY(launch(mode, cycle, active));
+    return collect(norms);
+}
+
+ma_status Engine::tick_ahead(Mode mode, const std::vector<char> &active,
+                             const std::vector<double> &thr, bool ahead,
+                             std::vector<double> &norms)
+{
+    if (active.size() != solves_.size() || thr.size() != solves_.size())
+        return fail(MA_ERR_ARG, "active mask size");
+    if (!fifo_.empty()) {
+        // the queued tick serves this call when it ran these solves
+        const Pending &f = fifo_.front();
+        bool same = f.cycle && f.mode == mode;
+        for (size_t i = 0; i < active.size() && same; ++i)
+            if (active[i] && (!f.active[i] || halted_[i]))
+                same = false;
+        if (!same)
+            MA_TRY(settle());
+    }
+    for (size_t i = 0; i < active.size(); ++i)
+        if (active[i])
+            arm(int(i), thr[i]);
+    if (fifo_.empty())
+        MA_TRY(launch(mode, true, active));
+    bool armed = false;
+    for (int i = 0; i < kMaxGrids; ++i)
+        armed |= armq_[i] != 0;
+    if (armed)
+        return fail(MA_ERR_DEVICE, "internal: thresholds changed with ticks in flight");
+    if (ahead && !profile_ && fifo_.size() == 1 && built_ && built_mode_ == mode &&
+        built_active_ == active)
+        MA_TRY(launch(mode, true, active));
+    return collect(norms);
 }
 
 // Capture one tick of mode into slot m: one graph, or (profiled form) one
@@ -1889,13 +2187,13 @@ ma_status Engine::capture(int m, Mode mode)
 
 ma_status Engine::tick(Mode mode, const std::vector<char> &active, std::vector<double> &norms)
 {
-    return run(mode, true, active, norms);
+    return plain(mode, true, active, norms);
 }
 
 ma_status Engine::norms_only(Mode mode, const std::vector<char> &active,
                              std::vector<double> &norms)
 {
-    return run(mode, false, active, norms);
+    return plain(mode, false, active, norms);
 }
 
 void Engine::take_profile(double *seconds, int *launches, double *bytes)

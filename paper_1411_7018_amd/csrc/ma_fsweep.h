@@ -55,10 +55,11 @@ constexpr int kFsMaxGrids = 64;
 struct FsList {
     int ngrids;
     int total;      // blocks over all grids
-    int pad[2];
+    unsigned long long stopped;  // bit s: solve s has stopped, skip it
     FsGrid g[kFsMaxGrids];
 };
 constexpr size_t fs_list_bytes(int ngrids) { return 16 + sizeof(FsGrid) * size_t(ngrids); }
+static_assert(offsetof(FsList, g) == 16, "list header is 16 bytes");
 
 template <int TX, int TY, int TZ>
 struct FsShape {
@@ -248,6 +249,8 @@ __global__ __launch_bounds__(NT) void k_bsweep(const FsList *__restrict__ L,
     while (g + 1 < ng && L->g[g + 1].start <= t)
         ++g;
     const FsGrid &G = L->g[g];
+    if ((L->stopped >> G.slot) & 1ull)
+        return;
     bsweep_tile<OP, TX, TY, TZ, NT>(G, t - G.start, su, ncount);
 }
 

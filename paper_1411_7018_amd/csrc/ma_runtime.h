@@ -125,6 +125,9 @@ struct SolveState {
                             // residual of the zero-interior start, and the
                             // FMG iteration is the first cycle
     long long fmg_nonconvex = 0;
+    // the phase's last two norms read (prev 0: only the phase's start is
+    // known), for the guess whether the tick being read will stop the solve
+    double last = 0.0, prev = 0.0;
 };
 
 // The FMG start of a solve (Section 4 protocol): zero the interior of u, take
@@ -137,6 +140,9 @@ ma_status fmg_start(ma_solver *s, double *u, const double *f, SolveState &st);
 // slot).  Per-solve outcomes land in the states; the return value reports
 // engine failures only.
 // init_only: stop after the Poisson phases.
-ma_status drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only = false);
+// ahead: let the engine queue a tick ahead of the stopping test (a closed
+// set of solves: the caller adds or removes none between steps).
+ma_status drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only = false,
+                     bool ahead = false);
 
 } // namespace mafas

@@ -240,7 +240,7 @@ ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigne
         return s->fail(MA_ERR_DEVICE, E->error());
     std::vector<SolveState *> states{&st};
     while (st.phase != SolveState::DONE) {
-        if (drive_step(*E, states) != MA_OK)
+        if (drive_step(*E, states, false, true) != MA_OK)
             return s->fail(MA_ERR_DEVICE, E->error());
     }
     std::vector<unsigned long long> nc, fb;
@@ -678,7 +678,8 @@ ma_status mafas::fmg_start(ma_solver *s, double *u, const double *f, SolveState 
 // ---------------------------------------------------------------------------
 // Per-solve phase machine shared by ma_solve, ma_solve_batch and ma_batch.
 // ---------------------------------------------------------------------------
-ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only)
+ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool init_only,
+                            bool ahead)
 {
     const int S = int(states.size());
     std::vector<char> act(S, 0);
@@ -712,7 +713,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 SolveState *st = states[i];
-                st->lin0 = nrm[i];
+                st->lin0 = st->last = nrm[i];
+                st->prev = 0.0;
                 if (!std::isfinite(nrm[i]))
                     finish(st, MA_ERR_NONFINITE, "Poisson initial residual is not finite");
                 else if (nrm[i] == 0.0 || eng.ref(i).s->p.init_max_cycles == 0)
@@ -721,17 +723,59 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                     st->phase = SolveState::INIT;
             }
     }
+    // A tick is queued ahead of the host's stopping test only while every
+    // live solve is in the phase being ticked and none can reach its cycle
+    // limit at the tick being read: every other reason to stop is one the
+    // device sees (the tolerance test and a non-finite norm, on the same sum
+    // through sum_threshold), so a solve that stops skips the tick queued
+    // after it.
+    auto only = [&](SolveState::Phase ph) {
+        for (int i = 0; i < S; ++i)
+            if (states[i] && states[i]->phase != SolveState::DONE && states[i]->phase != ph)
+                return false;
+        return true;
+    };
+    // the host's and the device's stopping decisions on the tick just read
+    auto agree = [&](int i, bool host_stop) {
+        return eng.halted(i) == host_stop;
+    };
+    // Whether the tick about to be read will leave solve st above its
+    // threshold c, guessed from its contraction so far (a factor of 10 per
+    // cycle before two norms are known) with a margin of 8: a tick queued
+    // ahead of a solve that then stops is skipped on the device but still
+    // costs its launches, while one not queued costs only a host round trip.
+    auto goes_on = [](const SolveState *st, double c) {
+        const double rho = st->prev > 0.0 ? st->last / st->prev : 0.1;
+        return st->last * rho > 8.0 * c;
+    };
     // 2. one linear V-cycle of the Poisson guess
+    bool init_ahead = false;
     if (select(SolveState::INIT)) {
-        MA_TRY(eng.tick(Engine::MODE_LAP, act, nrm));
+        std::vector<double> thr(S, -1.0);
+        bool spec = ahead && only(SolveState::INIT);
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                const ma_params &p = eng.ref(i).s->p;
+                const double c = p.init_tol * states[i]->lin0;
+                thr[i] = sum_threshold(c, p.n);
+                spec &= states[i]->rep.init_cycles + 2 <= p.init_max_cycles &&
+                        goes_on(states[i], c);
+            }
+        MA_TRY(eng.tick_ahead(Engine::MODE_LAP, act, thr, spec, nrm));
+        init_ahead = eng.pending() > 0;
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 SolveState *st = states[i];
                 const ma_params &p = eng.ref(i).s->p;
+                if (!agree(i, !std::isfinite(nrm[i]) || nrm[i] <= p.init_tol * st->lin0))
+                    return eng.fail(MA_ERR_DEVICE, "internal: device stopping flag disagrees "
+                                                   "with the Poisson stopping test");
                 double up, by;
                 eng.tick_cost(Engine::MODE_LAP, i, &up, &by);
                 st->rep.alg_bytes += by;
                 st->rep.init_cycles += 1;
+                st->prev = st->last;
+                st->last = nrm[i];
                 if (!std::isfinite(nrm[i]))
                     finish(st, MA_ERR_NONFINITE, "Poisson residual is not finite");
                 else if (nrm[i] <= p.init_tol * st->lin0 ||
@@ -739,7 +783,12 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                     st->phase = SolveState::MAIN0;
             }
     }
-    if (init_only)
+    // When this step's Poisson tick left one queued ahead, the solves that
+    // left the phase start the next one in the next step: a launch for them
+    // now would queue behind a tick that other solves have yet to read.  (A
+    // queued tick that no solve reads any more is one they all skip; the
+    // next launch waits for it.)
+    if (init_only || init_ahead)
         return MA_OK;
     // 3. residual of the initial guess (res0 of the stopping rule)
     if (select(SolveState::MAIN0)) {
@@ -755,6 +804,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                     r.cycles = 1;
                     r.outer = eng.mixed() ? 1 : 0;
                     r.res = r.history[0] = nrm[i];
+                    st->last = nrm[i];
+                    st->prev = 0.0;
                     r.rel_res = r.res0 > 0.0 ? r.res / r.res0 : 0.0;
                     if (!std::isfinite(nrm[i]))
                         finish(st, MA_ERR_NONFINITE, "residual after FMG is not finite");
@@ -768,7 +819,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                     }
                     continue;
                 }
-                st->rep.res0 = st->rep.res = nrm[i];
+                st->rep.res0 = st->rep.res = st->last = nrm[i];
+                st->prev = 0.0;
                 if (!std::isfinite(nrm[i]))
                     finish(st, MA_ERR_NONFINITE, "initial residual is not finite");
                 else if (nrm[i] == 0.0) {
@@ -783,12 +835,26 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
     }
     // 4. one V-cycle (FP64) or one outer correction (mixed)
     if (select(SolveState::MAIN)) {
-        MA_TRY(eng.tick(main_mode, act, nrm));
+        std::vector<double> thr(S, -1.0);
+        bool spec = ahead && only(SolveState::MAIN);
+        for (int i = 0; i < S; ++i)
+            if (act[i]) {
+                const ma_params &p = eng.ref(i).s->p;
+                const ma_report &r = states[i]->rep;
+                const double c = states[i]->tol * r.res0;
+                thr[i] = sum_threshold(c, p.n);
+                const int done = main_mode == Engine::MODE_MIXED ? r.outer : r.cycles;
+                spec &= done + 2 <= p.max_cycles && goes_on(states[i], c);
+            }
+        MA_TRY(eng.tick_ahead(main_mode, act, thr, spec, nrm));
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 SolveState *st = states[i];
                 const ma_params &p = eng.ref(i).s->p;
                 ma_report &r = st->rep;
+                if (!agree(i, !std::isfinite(nrm[i]) || nrm[i] <= st->tol * r.res0))
+                    return eng.fail(MA_ERR_DEVICE, "internal: device stopping flag disagrees "
+                                                   "with the stopping test");
                 double up, by;
                 eng.tick_cost(main_mode, i, &up, &by);
                 r.point_updates += up;
@@ -805,6 +871,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 if (steps - 1 < 64)
                     r.history[steps - 1] = nrm[i];
                 r.res = nrm[i];
+                st->prev = st->last;
+                st->last = nrm[i];
                 r.rel_res = r.res / r.res0;
                 if (!std::isfinite(r.res)) {
                     finish(st, MA_ERR_NONFINITE, "residual is not finite");
