@@ -156,8 +156,9 @@ struct ArmSet {
     int slot[kMaxGrids];
     double thr[kMaxGrids];
 };
-hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, const double *partials,
-                                 const NormRing &ring);
+// one block per grid of the norm list (grids = its grid count)
+hipError_t launch_batched_reduce(hipStream_t st, const BatchList *dlist, int grids,
+                                 const double *partials, const NormRing &ring);
 // base, stop: the list table and its header offsets as in NormRing, or null
 // before any list exists.
 hipError_t launch_arm(hipStream_t st, const ArmSet &a, double *thr, char *base,

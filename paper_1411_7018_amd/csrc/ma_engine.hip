@@ -430,9 +430,22 @@ __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__rest
     if ((L->stopped >> G.slot) & 1ull)
         return;
     const int cnt = G.gx * G.gy * G.gz;
+    // the same additions in the same order as one add per step, with the
+    // loads of eight steps in flight together
+    const double *pp = partials + G.pbase;
     double v = 0.0;
-    for (int q = threadIdx.x; q < cnt; q += 1024)
-        v += partials[G.pbase + q];
+    int q = int(threadIdx.x);
+    for (; q + 7 * 1024 < cnt; q += 8 * 1024) {
+        double a[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            a[m] = pp[q + m * 1024];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            v += a[m];
+    }
+    for (; q < cnt; q += 1024)
+        v += pp[q];
     v = wave_sum64(v);
     if ((threadIdx.x & 63) == 0)
         part[threadIdx.x >> 6] = v;
@@ -757,6 +770,32 @@ __global__ __launch_bounds__(kTailLdsThreads) void k_tail_lds(
         double *u = S + E.L.u[l];
         const double *b = S + E.L.b[l];
         const int cnt = colour_count<ORDER>(n);
+        if (cnt <= NT) {
+            // at most one candidate per thread: its position in the colour
+            // class, the same for every colour, is decomposed once per sweep
+            const int hn = n / 2;
+            const int ii = tid % hn, r = tid / hn;
+            const int jj = r % hn, kk = r / hn;
+            for (int c = 0; c < colours; ++c) {
+                int i, j, k;
+                if (ORDER == 0) {
+                    const int c0 = c & 1, c1 = c >> 1;
+                    k = 1 + kk;
+                    j = (((c0 + c1 + k) & 1) ? 1 : 2) + 2 * jj;
+                    i = (((c0 + j) & 1) ? 1 : 2) + 2 * ii;
+                } else {
+                    i = ((c & 1) ? 1 : 2) + 2 * ii;
+                    j = (((c >> 1) & 1) ? 1 : 2) + 2 * jj;
+                    k = (((c >> 2) & 1) ? 1 : 2) + 2 * kk;
+                }
+                if (tid < cnt && i <= n - 1 && j <= n - 1 && k <= n - 1) {
+                    const long p = i + sy * j + sz * k;
+                    sweep_node<OP>(u, b[p], p, sy, sz, G.s, G.hk, G.slot, ncount);
+                }
+                lds_barrier();
+            }
+            return;
+        }
         for (int c = 0; c < colours; ++c) {
             for (int q = tid; q < cnt; q += NT) {
                 int i, j, k;
@@ -966,10 +1005,12 @@ hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, lon
     return hipGetLastError();
 }
 
-hipError_t launch_batched_reduce(hipStream_t st, const BatchList *L, const double *partials,
-                                 const NormRing &ring)
+hipError_t launch_batched_reduce(hipStream_t st, const BatchList *L, int grids,
+                                 const double *partials, const NormRing &ring)
 {
-    hipLaunchKernelGGL(k_batched_reduce, dim3(kMaxGrids), dim3(1024), 0, st, L, partials, ring);
+    if (grids < 1 || grids > kMaxGrids)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batched_reduce, dim3(grids), dim3(1024), 0, st, L, partials, ring);
     return hipGetLastError();
 }
 
@@ -1865,7 +1906,7 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
         }
     }
     MA_TRY(go(mixed ? LK_RES32 : LK_NORM, norm_, 0));
-    E_HIP(launch_batched_reduce(stream_, L(norm_), partials_,
+    E_HIP(launch_batched_reduce(stream_, L(norm_), std::max(1, lng_[norm_]), partials_,
                                 NormRing{dnorm_, dstamp_, dseq_, dthr_, dl_,
                                          reinterpret_cast<const unsigned *>(dl_ + stoff_)}));
     return MA_OK;
@@ -1894,6 +1935,7 @@ std::vector<int> Engine::shape() const
     s.push_back(rroff_.empty() ? 0 : int(rroff_[0]));
     s.insert(s.end(), rrblocks_.begin(), rrblocks_.end());
     s.push_back(int(stoff_));
+    s.push_back(norm_ >= 0 ? lng_[norm_] : 0);
     return s;
 }
 
