@@ -207,6 +207,8 @@ ma_status ma_batch_tick(ma_batch *b, int *done_out)
         }
     if (!live)
         return MA_OK;
+    // the caller may have queued work for its solves since the last tick
+    b->eng.mark_user();
     if (drive_step(b->eng, ptr) != MA_OK)
         return b->fail(MA_ERR_DEVICE, b->eng.error());
     bool any_done = false;

@@ -225,6 +225,11 @@ class Engine {
     ma_status settle();
     // Ticks queued and not yet read.
     int pending() const { return int(fifo_.size()); }
+    // Work may have been queued on the caller's stream since the engine's
+    // last launch: the next launch orders itself after it.  set() implies
+    // this; within one call, launches order after each other on the engine
+    // stream and skip the cross-stream wait.
+    void mark_user() { user_dirty_ = true; }
     // The device halt flag of solve i as last seen by the host.
     bool halted(int i) const { return halted_[i] != 0; }
     ma_status reset_counters(int slot);  // slot < 0: all
@@ -273,6 +278,7 @@ class Engine {
     std::vector<SolveRef> solves_;
     hipStream_t user_ = nullptr, stream_ = nullptr;
     hipEvent_t ev_in_ = nullptr;
+    bool user_dirty_ = true;
     bool graphs_ = true, profile_ = false;
     std::string err_;
     int D_ = 0;      // multi-block depth of the active solves

@@ -1158,6 +1158,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     // tables, which every rebuild rewrites; what it holds as a plain kernel
     // argument is the partials buffer, whose reallocation drops the graphs.
     solves_ = solves;
+    user_dirty_ = true;
     fs_src_.assign(solves_.size(), nullptr);   // contents of f unknown: rebuild
     user_ = user;
     graphs_ = graphs;
@@ -1951,8 +1952,11 @@ ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
         MA_TRY(rebuild(mode, active));
     }
     MA_TRY(flush_arms());
-    E_HIP(hipEventRecord(ev_in_, user_));
-    E_HIP(hipStreamWaitEvent(stream_, ev_in_, 0));
+    if (user_dirty_) {
+        E_HIP(hipEventRecord(ev_in_, user_));
+        E_HIP(hipStreamWaitEvent(stream_, ev_in_, 0));
+        user_dirty_ = false;
+    }
     if (cycle)
         MA_TRY(refresh_fs(mode, active));
     const int m = int(mode) + (profile_ ? 3 : 0);

@@ -707,6 +707,7 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 const SolveRef &r = eng.ref(i);
                 if (launch_poisson_rhs(eng.user(), r.s->p.n, r.f, r.s->R) != hipSuccess)
                     return MA_ERR_DEVICE;
+                eng.mark_user();
                 eng.rhs_changed(i);
             }
         MA_TRY(eng.norms_only(Engine::MODE_LAP, act, nrm));
