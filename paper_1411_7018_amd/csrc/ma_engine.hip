@@ -1907,7 +1907,9 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
         }
     }
     MA_TRY(go(mixed ? LK_RES32 : LK_NORM, norm_, 0));
-    E_HIP(launch_batched_reduce(stream_, L(norm_), std::max(1, lng_[norm_]), partials_,
+    // one block per solve of the engine (blocks past the list's grids
+    // return): the launch shape does not change when solves pause or stop
+    E_HIP(launch_batched_reduce(stream_, L(norm_), int(solves_.size()), partials_,
                                 NormRing{dnorm_, dstamp_, dseq_, dthr_, dl_,
                                          reinterpret_cast<const unsigned *>(dl_ + stoff_)}));
     return MA_OK;
@@ -1936,7 +1938,7 @@ std::vector<int> Engine::shape() const
     s.push_back(rroff_.empty() ? 0 : int(rroff_[0]));
     s.insert(s.end(), rrblocks_.begin(), rrblocks_.end());
     s.push_back(int(stoff_));
-    s.push_back(norm_ >= 0 ? lng_[norm_] : 0);
+    s.push_back(int(solves_.size()));
     return s;
 }
 
