@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size): profiles/k_batched_sweep_quadratic129_counters.md.  Valid for
 # the k_batched sweep kernel as profiled; reset to None when it changes.
-TRAFFIC = {("quadratic129", "fp64"): 31600332}
+TRAFFIC = {("quadratic129", "fp64"): 31592960}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
