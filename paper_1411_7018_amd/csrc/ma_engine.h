@@ -120,7 +120,7 @@ enum ListKind {
     LK_RESIDUAL,   // p: u, F, r                     items: interior rows
     LK_RESTRICT,   // p: uf, rf, wc, uc, bc          items: coarse rows (n = fine n)
     LK_PROLONG,    // p: uf, uc, wc                  items: fine interior rows
-    LK_NORM,       // p: u, F, partials              items: interior rows
+    LK_NORM,       // p: u, F, partials              items: interior rows x plane chunks
     LK_MSWEEP,     // p: d, b, U                     items: rows of one colour
     LK_MRESIDUAL,  // p: d, b, U, r                  items: interior rows
     LK_MRESTRICT,  // p: df, rf, Uc, wc, dc, bc      items: coarse rows (n = fine n)
@@ -131,6 +131,8 @@ enum ListKind {
     LK_RES32,      // p: u64, f, b0, partials        items: interior rows
 };
 
+// planes per work item of a norm list (a lane walks them along z)
+constexpr int kNormPlanes = 8;
 void item_dims(int kind, int order, int n, int *gx, int *gy, int *gz);
 
 // blocks: grid size (a multiple of 8; blocks are split evenly over the XCDs)

@@ -72,6 +72,18 @@ __device__ __forceinline__ double resid_node(PU u, PF F, long p, long sy, long s
     return resid_val<OP>(u, p, sy, sz, s, F[p]);
 }
 
+// The same residual from the node's 3x3 neighbourhoods in the planes below,
+// at and above it (D, C, U point at the centre; x stride 1, y stride 3),
+// e.g. held in registers by a lane walking along z.
+template <int OP>
+__device__ __forceinline__ double resid_win(const double *D, const double *C, const double *U,
+                                            double s, double Fv)
+{
+    if (OP == OP_MA)
+        return Fv - det3(hessian3(D, C, U, 1, -1, 3, s, 0.25 * s));
+    return Fv - laplacian3(D, C, U, 1, -1, 3, s);
+}
+
 // b_H at a coarse interior node: S_H(w_H) + I_h^H r (Algorithm 1, step 3),
 // with w_H the injection of u.  The coarse node sits at fine index fu of uf
 // (strides uy, uz) and fr of rf (strides ry, rz); sc = 1/H^2.
@@ -124,24 +136,58 @@ __device__ __forceinline__ void restrict_node(int nf, int I, int J, int K, PU uf
 
 // Trilinear prolongation of the coarse correction (u_H - w_H) added at
 // fine interior node (i, j, k) of the fine grid nf (Algorithm 1, step 5).
-// T: double or float.
+// T: double or float.  A node has one or two coarse neighbours along each
+// axis (two where its index is odd), added in the order of loops over the
+// (k, j, i) offsets.  The j and k parities are the same for a whole row, so
+// one of four fixed shapes runs; inside it every load is issued before any
+// is used (a lane with even i reads its first x neighbour again for the
+// second, and the select drops it), and the sum is that of the plain loops.
+template <int NJ, int NK, typename T, typename PC>
+__device__ __forceinline__ T prolong_sum(long cy, long cz, int I0, int J0, int K0, int oi, T w,
+                                         PC uc, PC wc)
+{
+    T e[NK * NJ * 2];
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+        for (int b = 0; b < NJ; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const long q = (I0 + (a <= oi ? a : 0)) + cy * (J0 + b) + cz * (K0 + c);
+                e[(c * NJ + b) * 2 + a] = uc[q] - wc[q];
+            }
+    T d = T(0);
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+        for (int b = 0; b < NJ; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                if (a <= oi)
+                    d += w * e[(c * NJ + b) * 2 + a];
+    return d;
+}
+
 template <typename T, typename PF, typename PC>
 __device__ __forceinline__ void prolong_node(int nf, int i, int j, int k, PF uf, PC uc, PC wc)
 {
     const int nc = nf / 2;
     const long sy = nf + 1, sz = sy * sy, cy = nc + 1, cz = cy * cy;
-    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+    const int oi = i & 1, oj = j & 1, ok = k & 1;
     const int I0 = i >> 1, J0 = j >> 1, K0 = k >> 1;
     const long p = i + sy * j + sz * k;
     const T one = T(1), half = T(0.5);
-    const T wi = (i & 1) ? half : one, wj = (j & 1) ? half : one, wk = (k & 1) ? half : one;
-    T d = T(0);
-    for (int c = 0; c < nk; ++c)
-        for (int b = 0; b < nj; ++b)
-            for (int a = 0; a < ni; ++a) {
-                const long q = (I0 + a) + cy * (J0 + b) + cz * (K0 + c);
-                d += (wk * wj * wi) * (uc[q] - wc[q]);
-            }
+    const T wi = oi ? half : one, wj = oj ? half : one, wk = ok ? half : one;
+    const T w = wk * wj * wi;
+    T d;
+    if (oj == 0 && ok == 0)
+        d = prolong_sum<1, 1, T>(cy, cz, I0, J0, K0, oi, w, uc, wc);
+    else if (ok == 0)
+        d = prolong_sum<2, 1, T>(cy, cz, I0, J0, K0, oi, w, uc, wc);
+    else if (oj == 0)
+        d = prolong_sum<1, 2, T>(cy, cz, I0, J0, K0, oi, w, uc, wc);
+    else
+        d = prolong_sum<2, 2, T>(cy, cz, I0, J0, K0, oi, w, uc, wc);
     uf[p] += d;
 }
 
@@ -286,7 +332,43 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
                 pt_msweep(G, p, sy, sz, ncount, nfall);
             }
         }
-    } else if (KIND == LK_RESIDUAL || KIND == LK_NORM || KIND == LK_RES32) {
+    } else if (KIND == LK_NORM) {
+        // Squared residuals of a 64-node row segment over kNormPlanes planes:
+        // each lane walks along z keeping the 3x3 neighbourhoods of three
+        // planes in registers, 9 loads per node instead of the 19 of the
+        // gathered stencil.
+        const int i = 1 + bx * 64 + t, j = 1 + by;
+        const int k0 = 1 + bz * kNormPlanes, k1 = min(k0 + kNormPlanes, n);
+        const int ic = min(i, n - 1);
+        const auto u = gptr<const double>(G.p[0]);
+        const auto F = gptr<const double>(G.p[1]);
+        double P0[9], P1[9], P2[9];
+        auto load = [&](double *P, int kk) {
+            const long b0 = ic + sy * j + sz * kk;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    P[(dy + 1) * 3 + (dx + 1)] = u[b0 + dx + sy * dy];
+        };
+        load(P0, k0 - 1);
+        load(P1, k0);
+        double acc = 0.0;
+        for (int k = k0; k < k1; ++k) {
+            load(P2, k + 1);
+            const double rv = resid_win<OP>(P0 + 4, P1 + 4, P2 + 4, G.s, F[ic + sy * j + sz * k]);
+            if (i <= n - 1)
+                acc += rv * rv;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                P0[q] = P1[q];
+                P1[q] = P2[q];
+            }
+        }
+        const double sum = wave_sum64(acc);
+        if (t == 0)
+            static_cast<double *>(G.p[2])[G.pbase + bx + G.gx * (by + G.gy * bz)] = sum;
+    } else if (KIND == LK_RESIDUAL || KIND == LK_RES32) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
         double rv = 0.0;
         if (i <= n - 1) {
@@ -297,12 +379,11 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
             if (KIND == LK_RES32)
                 static_cast<float *>(G.p[2])[p] = float(rv);
         }
-        if (KIND != LK_RESIDUAL) {
+        if (KIND == LK_RES32) {
             const double sum = wave_sum64(rv * rv);
             if (t == 0) {
                 const int local = bx + G.gx * (by + G.gy * bz);
-                double *part = static_cast<double *>(KIND == LK_NORM ? G.p[2] : G.p[3]);
-                part[G.pbase + local] = sum;
+                static_cast<double *>(G.p[3])[G.pbase + local] = sum;
             }
         }
     } else if (KIND == LK_RESTRICT || KIND == LK_MRESTRICT || KIND == LK_INJECT) {
@@ -373,9 +454,7 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
     for (; it < hi; it += bpx) {
         while (g + 1 < ng && L->g[g + 1].start <= it)
             ++g;
-        const GridItem &G = L->g[g];
-        if ((stopped >> G.slot) & 1ull)
-            continue;
+        const GridItem G = L->g[g];   // the whole descriptor in one set of loads
         const int local = it - G.start;
         const int bx = local % G.gx;
         int rest = local / G.gx;
@@ -383,7 +462,9 @@ __global__ __launch_bounds__(64) void k_batched(const BatchList *__restrict__ L,
         rest /= G.w;
         const int bz = rest % G.gz;
         const int by = (rest / G.gz) * G.w + jj;
-        if (by < G.gy)
+        // the stopped test after the descriptor's other fields, so they load
+        // together
+        if (by < G.gy && !((stopped >> G.slot) & 1ull))
             run_item<KIND, OP, ORDER, RMODE>(G, bx, by, bz, color, int(threadIdx.x), ncount,
                                              nfall);
     }
@@ -657,7 +738,7 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
     int g = 0;
     while (g + 1 < ng && Lst->g[g + 1].start <= t)
         ++g;
-    const RrGrid &G = Lst->g[g];
+    const RrGrid G = Lst->g[g];   // the whole descriptor in one set of loads
     if ((Lst->stopped >> G.slot) & 1ull)
         return;
     const int tile = t - G.start;
@@ -670,24 +751,55 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
     const int tid = int(threadIdx.x);
     const auto uf = to_global(G.uf);
     const auto F = to_global(G.F);
-    for (int el = tid; el < R::NU; el += NT) {
-        const int lz = el / (RU * RU), rem = el - lz * (RU * RU);
-        const int ly = rem / RU, lx = rem - ly * RU;
-        const int gx = ux0 + lx, gy = uy0 + ly, gz = uz0 + lz;
-        const bool in = gx >= 0 && gx <= nf && gy >= 0 && gy <= nf && gz >= 0 && gz <= nf;
-        su[el] = in ? uf[gx + fy * gy + fz * gz] : 0.0;
+    // every global load of a thread is issued before the first is used
+    // (unrolled over the thread's elements; outside the grid a load reads
+    // node 0 and is discarded)
+    constexpr int KU = (R::NU + NT - 1) / NT, KR = (R::NR + NT - 1) / NT;
+    {
+        double v[KU];
+#pragma unroll
+        for (int m = 0; m < KU; ++m) {
+            const int el = tid + m * NT;
+            const int lz = el / (RU * RU), rem = el - lz * (RU * RU);
+            const int ly = rem / RU, lx = rem - ly * RU;
+            const int gx = ux0 + lx, gy = uy0 + ly, gz = uz0 + lz;
+            const bool in = el < R::NU && gx >= 0 && gx <= nf && gy >= 0 && gy <= nf && gz >= 0 &&
+                            gz <= nf;
+            const double x = uf[in ? gx + fy * gy + fz * gz : 0];
+            v[m] = in ? x : 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < KU; ++m)
+            if (tid + m * NT < R::NU)
+                su[tid + m * NT] = v[m];
+    }
+    // right-hand side of the fine interior nodes of the footprint (origin
+    // ux0 + 1), loaded while the block waits at the barrier
+    double fv[KR];
+#pragma unroll
+    for (int m = 0; m < KR; ++m) {
+        const int el = tid + m * NT;
+        const int lz = el / (RR * RR), rem = el - lz * (RR * RR);
+        const int ly = rem / RR, lx = rem - ly * RR;
+        const int gx = ux0 + 1 + lx, gy = uy0 + 1 + ly, gz = uz0 + 1 + lz;
+        const bool in = el < R::NR && gx >= 1 && gx <= nf - 1 && gy >= 1 && gy <= nf - 1 &&
+                        gz >= 1 && gz <= nf - 1;
+        fv[m] = F[in ? gx + fy * gy + fz * gz : 0];
     }
     lds_barrier();
-    // r on the fine interior nodes of the footprint (origin ux0 + 1)
-    for (int el = tid; el < R::NR; el += NT) {
+    // r on the fine interior nodes of the footprint
+#pragma unroll
+    for (int m = 0; m < KR; ++m) {
+        const int el = tid + m * NT;
+        if (el >= R::NR)
+            break;
         const int lz = el / (RR * RR), rem = el - lz * (RR * RR);
         const int ly = rem / RR, lx = rem - ly * RR;
         const int gx = ux0 + 1 + lx, gy = uy0 + 1 + ly, gz = uz0 + 1 + lz;
         double rv = 0.0;
         if (gx >= 1 && gx <= nf - 1 && gy >= 1 && gy <= nf - 1 && gz >= 1 && gz <= nf - 1) {
             const long pu = (lx + 1) + RU * (ly + 1) + long(RU * RU) * (lz + 1);
-            rv = resid_val<OP>(static_cast<const double *>(su), pu, RU, RU * RU, G.s,
-                               F[gx + fy * gy + fz * gz]);
+            rv = resid_val<OP>(static_cast<const double *>(su), pu, RU, RU * RU, G.s, fv[m]);
         }
         sr[el] = rv;
     }
@@ -757,9 +869,25 @@ __global__ __launch_bounds__(kTailLdsThreads) void k_tail_lds(
         const auto gu = gptr<const double>(E.lv[0].sw.p[0]);
         const auto gb = gptr<const double>(E.lv[0].sw.p[1]);
         double *u = S + E.L.u[0], *b = S + E.L.b[0];
-        for (int q = tid; q < N; q += NT) {
-            u[q] = gu[q];
-            b[q] = gb[q];
+        // five elements per thread with their loads in flight together (a
+        // 17^3 top level is 4913 nodes)
+        constexpr int KQ = 5;
+        for (int q0 = 0; q0 < N; q0 += KQ * NT) {
+            double vu[KQ], vb[KQ];
+#pragma unroll
+            for (int m = 0; m < KQ; ++m) {
+                const int q = q0 + tid + m * NT;
+                vu[m] = gu[q < N ? q : 0];
+                vb[m] = gb[q < N ? q : 0];
+            }
+#pragma unroll
+            for (int m = 0; m < KQ; ++m) {
+                const int q = q0 + tid + m * NT;
+                if (q < N) {
+                    u[q] = vu[m];
+                    b[q] = vb[m];
+                }
+            }
         }
     }
     lds_barrier();
@@ -946,6 +1074,11 @@ void item_dims(int kind, int order, int n, int *gx, int *gy, int *gz)
         *gx = (n + 1 + 63) / 64;
         *gy = n + 1;
         *gz = n + 1;
+        break;
+    case LK_NORM:  // interior rows, planes in chunks of kNormPlanes
+        *gx = (n - 1 + 63) / 64;
+        *gy = n - 1;
+        *gz = (n - 1 + kNormPlanes - 1) / kNormPlanes;
         break;
     default:  // interior rows
         *gx = (n - 1 + 63) / 64;
@@ -1207,12 +1340,15 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hcount_),
                             2 * kMaxGrids * sizeof(unsigned long long)));
     }
+    // partial sums: one per work item of the norm list of a tick, whose kind
+    // is LK_NORM (FP64 and Poisson ticks) or LK_RES32 (mixed corrections)
     size_t need = 0;
     for (const SolveRef &r : solves_)
         if (r.s) {
-            int gx, gy, gz;
+            int gx, gy, gz, hx, hy, hz;
             item_dims(LK_NORM, 0, r.s->p.n, &gx, &gy, &gz);
-            need += size_t(gx) * gy * gz;
+            item_dims(LK_RES32, 0, r.s->p.n, &hx, &hy, &hz);
+            need += std::max(size_t(gx) * gy * gz, size_t(hx) * hy * hz);
         }
     if (need > partials_cap_) {
         E_HIP(hipStreamSynchronize(stream_));

@@ -161,7 +161,10 @@ __device__ __forceinline__ void bsweep_tile(const FsGrid &G, int tile, double *_
     for (int m = 0; m < M3; ++m)
         f3[m] = fetch(3, m);
 
-    // ---- the block and its halo into LDS (0 outside the grid)
+    // ---- the block and its halo into LDS (0 outside the grid): every load
+    // of the lane first, then the LDS writes, so all of them are in flight
+    // together
+    double lv[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
         const int el = tid + k * NT;
@@ -171,8 +174,15 @@ __device__ __forceinline__ void bsweep_tile(const FsGrid &G, int tile, double *_
         const bool in = el < S::NL && gx >= 0 && gx <= n && gy >= 0 && gy <= n && gz >= 0 &&
                         gz <= n;
         const double v = uin[in ? gx + sy * gy + sz * gz : 0];
+        lv[k] = in ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int el = tid + k * NT;
+        const int lz = el / PL, rem = el - (el / PL) * PL;
+        const int ly = rem / LX, lx = rem - (rem / LX) * LX;
         if (el < S::NL)
-            su[lz * PL + ly * LX + (lx & 1) * HW + (lx >> 1)] = in ? v : 0.0;
+            su[lz * PL + ly * LX + (lx & 1) * HW + (lx >> 1)] = lv[k];
     }
     lds_barrier();
 
@@ -248,7 +258,7 @@ __global__ __launch_bounds__(NT) void k_bsweep(const FsList *__restrict__ L,
     int g = 0;
     while (g + 1 < ng && L->g[g + 1].start <= t)
         ++g;
-    const FsGrid &G = L->g[g];
+    const FsGrid G = L->g[g];   // the whole descriptor in one set of loads
     if ((L->stopped >> G.slot) & 1ull)
         return;
     bsweep_tile<OP, TX, TY, TZ, NT>(G, t - G.start, su, ncount);

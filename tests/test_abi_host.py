@@ -13,7 +13,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     names = set()
     for h in ("ma.h", "ma2d.h"):
-        src = open(os.path.join(ROOT, "include", h)).read()
+        with open(os.path.join(ROOT, "include", h)) as fh:
+            src = fh.read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         names |= set(re.findall(r"\b(ma2?d?_[a-z_0-9]+)\s*\(", src))
     return sorted(names)
@@ -129,3 +130,36 @@ def test_2d_params_and_footprint():
     assert L.ma2d_footprint_bytes(p) == 0
     with pytest.raises(L.MAError):
         L.ma2d_create(p, None)
+
+
+def test_stopping_threshold_matches_the_host_test():
+    """The device stops a solve when its sum of squares x satisfies x <= T
+    (T from sum_threshold); the host stops it when sqrt(x h h h) <= c.  The
+    two tests must agree on every double: T passes, the next double up
+    fails, and x well below or above T decides the same way on both sides.
+    (Host function of the library, reached through its C++ symbol.)"""
+    import math
+
+    import numpy as np
+
+    from paper_1411_7018_amd import _lib
+
+    f = getattr(_lib.lib(), "_ZN5mafas13sum_thresholdEdi")
+    f.argtypes = [ctypes.c_double, ctypes.c_int]
+    f.restype = ctypes.c_double
+
+    def host(x, c, n):
+        h = 1.0 / float(n)
+        return math.sqrt(x * h * h * h) <= c
+
+    rng = np.random.default_rng(3)
+    cases = [(0.0, 2), (1e-300, 16), (3.7e-9, 128), (1.0, 3), (2.5e150, 384)]
+    cases += [(float(10.0 ** rng.uniform(-30, 10)), int(rng.integers(2, 1500))) for _ in range(300)]
+    for c, n in cases:
+        t = f(c, n)
+        assert t >= 0.0 and host(t, c, n), (c, n, t)
+        up = float(np.nextafter(t, np.inf)) if t < np.finfo(float).max else float("inf")
+        assert not host(up, c, n), (c, n, t)
+        for x in (t * 0.5, t * 0.999999, up * 1.000001, t * 2.0, 0.0):
+            assert host(x, c, n) == (x <= t), (c, n, x, t)
+    assert f(-1.0, 16) < 0.0 and f(float("nan"), 16) < 0.0
