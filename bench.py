@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size): profiles/k_batched_sweep_quadratic129_counters.md.  Valid for
 # the k_batched sweep kernel as profiled; reset to None when it changes.
+SERVE_RATE = 30.0   # served stream: Poisson arrivals per second
 TRAFFIC = {("quadratic129", "fp64"): 31592960}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
@@ -79,7 +80,8 @@ def parse():
                     help="only run 20 plain device copies of MB megabytes (counter "
                          "calibration for the traffic figures) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rate", type=float, default=None, help="served: arrivals per second")
+    ap.add_argument("--rate", type=float, default=None,
+                    help=f"served: arrivals per second (default {SERVE_RATE:g})")
     ap.add_argument("--budget-gb", type=float, default=None, help="served: HBM budget")
     ap.add_argument("--lanes", default="65/129/257/385",
                     help="served: size classes in points per side, '/' between classes and "
@@ -406,26 +408,15 @@ def run_batch(args, precision):
 def run_served(args, precision):
     import torch
 
-    from paper_1411_7018_amd import Solver, problems as P
+    from paper_1411_7018_amd import problems as P
     from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
 
     count = args.steps or 256
     warmup = 8 if args.warmup is None else args.warmup
-    rate = args.rate
-    if rate is None:
-        # 0.8 x the plain FP64 capacity: mean solo service time over the size mix
-        tsvc = 0.0
-        for n, w in zip(P.SERVE_SIZES, P.SERVE_WEIGHTS):
-            u, f = P.make_device("exp_cos", n, 11)
-            s = Solver(n)
-            s.solve(u.clone(), f)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s.solve(u, f)
-            torch.cuda.synchronize()
-            tsvc += w * (time.perf_counter() - t0)
-            del s, u, f
-        rate = 0.8 / tsvc
+    # a fixed arrival rate, below what one GPU serves of this size mix (about
+    # 38 solves/s in FP64): the latencies then measure service and ordinary
+    # queueing, not a queue that grows without bound
+    rate = SERVE_RATE if args.rate is None else args.rate
     budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else GpuBackend.budget_default()
     lanes = None
     if args.lanes and args.lanes != "none":
