@@ -227,6 +227,9 @@ class Engine {
     ma_status settle();
     // Ticks queued and not yet read.
     int pending() const { return int(fifo_.size()); }
+    // Drop queued ticks after a failed step and resynchronise the host's
+    // view of the stopping state with the device.
+    ma_status abandon();
     // Work may have been queued on the caller's stream since the engine's
     // last launch: the next launch orders itself after it.  set() implies
     // this; within one call, launches order after each other on the engine

@@ -1286,7 +1286,10 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
-    MA_TRY(settle());
+    // ticks still queued: skipped ones are waited for; a live one is left by
+    // a step that failed, and is dropped with the state resynchronised
+    if (settle() != MA_OK)
+        MA_TRY(abandon());
     // A captured tick reads the grids' operand pointers from the device
     // tables, which every rebuild rewrites; what it holds as a plain kernel
     // argument is the partials buffer, whose reallocation drops the graphs.
@@ -2229,6 +2232,27 @@ double sum_threshold(double c, int n)
             hi = mid;
     }
     return val(lo);
+}
+
+// Drop every queued tick, whatever it ran: after a failed step the host no
+// longer reads them.  The device's per-slot sums counts are read back and
+// every slot is re-armed before its next launch (a dropped tick may have
+// stopped solves the host did not see stop).
+ma_status Engine::abandon()
+{
+    if (!stream_)
+        return MA_OK;
+    E_HIP(hipStreamSynchronize(stream_));
+    while (!fifo_.empty()) {
+        evpool_.push_back(fifo_.front().ev);
+        fifo_.pop_front();
+    }
+    E_HIP(hipMemcpy(seq_.data(), dseq_, kMaxGrids * sizeof(unsigned), hipMemcpyDeviceToHost));
+    for (int i = 0; i < kMaxGrids; ++i) {
+        thr_dev_[i] = std::numeric_limits<double>::quiet_NaN();   // never equal: re-arm
+        halted_[i] = 0;
+    }
+    return MA_OK;
 }
 
 // Queue (slot, thr) for the next launch unless the device already holds
