@@ -102,6 +102,13 @@ def roofline(reps, traffic=None):
            "alg_bytes_per_launch": by / max(la, 1)}
     if traffic is not None:
         out["traffic_unit"] = "bytes per launch (counters)"
+    if la == 0:
+        # a grid of n <= coarse_n has no row-kernel sweep: all its levels run
+        # in one single-workgroup launch per cycle, bound by the dependent
+        # FP64 chain of each phase rather than by memory
+        out.update({"bound": "latency", "achieved": None, "frac": None,
+                    "kernel": "none: every level runs in k_tail_lds (one workgroup per "
+                              "solve, latency bound)"})
     return out
 
 
