@@ -191,6 +191,68 @@ __device__ __forceinline__ void prolong_node(int nf, int i, int j, int k, PF uf,
     uf[p] += d;
 }
 
+// The same prolongation for the 64 fine nodes i = 1 + 64 bx + t of one row
+// kernel item, every lane of the wave taking part.  Lane t loads the coarse
+// column its node starts from (i >> 1); a node with odd i also needs the next
+// column, which is the column lane t + 1 starts from, so it takes that
+// difference from lane t + 1 instead of loading it.  Half the coarse loads of
+// prolong_node, and the same terms summed in the same order.
+template <int NJ, int NK, typename T, typename PC>
+__device__ __forceinline__ T prolong_sum_row(long cy, long cz, int X, int J0, int K0, int oi, T w,
+                                             PC uc, PC wc)
+{
+    T a[NK * NJ], b[NK * NJ];
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+        for (int m = 0; m < NJ; ++m) {
+            const long q = X + cy * (J0 + m) + cz * (K0 + c);
+            a[c * NJ + m] = uc[q];
+            b[c * NJ + m] = wc[q];
+        }
+    T d = T(0);
+#pragma unroll
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+        for (int m = 0; m < NJ; ++m) {
+            const T e0 = a[c * NJ + m] - b[c * NJ + m];
+            const T e1 = __shfl_down(e0, 1, 64);
+            d += w * e0;
+            if (oi)
+                d += w * e1;
+        }
+    return d;
+}
+
+template <typename T>
+__device__ __forceinline__ void prolong_row(const GridItem &G, int bx, int t, int j, int k)
+{
+    const int nf = G.n, nc = nf / 2;
+    const long sy = nf + 1, sz = sy * sy, cy = nc + 1, cz = cy * cy;
+    const int i = 1 + bx * 64 + t;
+    const int oi = i & 1, oj = j & 1, ok = k & 1;
+    const int J0 = j >> 1, K0 = k >> 1;
+    // i >> 1; clamped only for lanes past the end of the row, whose sums
+    // are not used
+    const int X = min(bx * 32 + (t >> 1) + (t & 1), nc);
+    const T one = T(1), half = T(0.5);
+    const T wi = oi ? half : one, wj = oj ? half : one, wk = ok ? half : one;
+    const T w = wk * wj * wi;
+    const auto uc = gptr<const T>(G.p[1]);
+    const auto wc = gptr<const T>(G.p[2]);
+    T d;
+    if (oj == 0 && ok == 0)
+        d = prolong_sum_row<1, 1, T>(cy, cz, X, J0, K0, oi, w, uc, wc);
+    else if (ok == 0)
+        d = prolong_sum_row<2, 1, T>(cy, cz, X, J0, K0, oi, w, uc, wc);
+    else if (oj == 0)
+        d = prolong_sum_row<1, 2, T>(cy, cz, X, J0, K0, oi, w, uc, wc);
+    else
+        d = prolong_sum_row<2, 2, T>(cy, cz, X, J0, K0, oi, w, uc, wc);
+    if (i <= nf - 1)
+        gptr<T>(G.p[0])[i + sy * j + sz * k] += d;
+}
+
 // The same phases on a grid of a device table (global memory).
 template <int OP>
 __device__ __forceinline__ void pt_sweep(const GridItem &G, long p, long sy, long sz,
@@ -401,13 +463,11 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
             }
         }
     } else if (KIND == LK_PROLONG || KIND == LK_MPROLONG) {
-        const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
-        if (i <= n - 1) {
-            if (KIND == LK_PROLONG)
-                pt_prolong<double>(G, i, j, k);
-            else
-                pt_prolong<float>(G, i, j, k);
-        }
+        // every lane takes part (lanes exchange coarse differences)
+        if (KIND == LK_PROLONG)
+            prolong_row<double>(G, bx, t, 1 + by, 1 + bz);
+        else
+            prolong_row<float>(G, bx, t, 1 + by, 1 + bz);
     } else if (KIND == LK_MRESIDUAL) {
         const int i = 1 + bx * 64 + t, j = 1 + by, k = 1 + bz;
         if (i <= n - 1)
