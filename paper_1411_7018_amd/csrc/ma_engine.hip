@@ -781,15 +781,20 @@ struct RrShape {
     static constexpr int RU = 2 * TC + 3;    // u footprint per side (fine nodes)
     static constexpr int RR = 2 * TC + 1;    // r footprint per side
     static constexpr int NU = RU * RU * RU, NR = RR * RR * RR;
+    // LDS row strides, padded to 4 mod 8 doubles: the restriction reads the
+    // footprints at x stride 2, and with rows of 4 mod 8 doubles the 4 x 4
+    // coarse nodes of a plane fall on distinct bank pairs
+    static constexpr int UX = RU + (12 - RU % 8) % 8, RX = RR + (12 - RR % 8) % 8;
+    static constexpr int SU = UX * RU * RU, SR = RX * RR * RR;   // LDS doubles
 };
 
 template <int OP, int RMODE, int TC, int NT>
 __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst)
 {
     using R = RrShape<TC>;
-    constexpr int RU = R::RU, RR = R::RR;
-    __shared__ double su[R::NU];
-    __shared__ double sr[R::NR];
+    constexpr int RU = R::RU, RR = R::RR, UX = R::UX, RX = R::RX;
+    __shared__ double su[R::SU];
+    __shared__ double sr[R::SR];
     const int total = Lst->total;
     const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
     if (t >= total)
@@ -811,57 +816,82 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
     const int tid = int(threadIdx.x);
     const auto uf = to_global(G.uf);
     const auto F = to_global(G.F);
-    // every global load of a thread is issued before the first is used
-    // (unrolled over the thread's elements; outside the grid a load reads
-    // node 0 and is discarded)
-    constexpr int KU = (R::NU + NT - 1) / NT, KR = (R::NR + NT - 1) / NT;
+    // A thread takes one column (x, y) of a footprint and a run of its
+    // planes: the column's offset and bounds are worked out once, and each
+    // plane adds a plane stride.  Every global load of a thread is issued
+    // before the first is used; outside the grid a load reads node 0 and is
+    // discarded.
+    constexpr int CU2 = RU * RU, GU = NT / CU2, PU = (RU + GU - 1) / GU;   // u footprint
+    constexpr int CR2 = RR * RR, GR = NT / CR2, PR = (RR + GR - 1) / GR;   // r footprint
+    static_assert(GU >= 1 && GR >= 1, "a block covers every column of a footprint");
     {
-        double v[KU];
+        const int col = tid % CU2, grp = tid / CU2;
+        const int lx = col % RU, ly = col / RU, lz0 = grp * PU;
+        const int gx = ux0 + lx, gy = uy0 + ly;
+        const bool cin = grp < GU && gx >= 0 && gx <= nf && gy >= 0 && gy <= nf;
+        const long co = gx + fy * gy;
+        double v[PU];
 #pragma unroll
-        for (int m = 0; m < KU; ++m) {
-            const int el = tid + m * NT;
-            const int lz = el / (RU * RU), rem = el - lz * (RU * RU);
-            const int ly = rem / RU, lx = rem - ly * RU;
-            const int gx = ux0 + lx, gy = uy0 + ly, gz = uz0 + lz;
-            const bool in = el < R::NU && gx >= 0 && gx <= nf && gy >= 0 && gy <= nf && gz >= 0 &&
-                            gz <= nf;
-            const double x = uf[in ? gx + fy * gy + fz * gz : 0];
+        for (int m = 0; m < PU; ++m) {
+            const int gz = uz0 + lz0 + m;
+            const bool in = cin && lz0 + m < RU && gz >= 0 && gz <= nf;
+            const double x = uf[in ? co + fz * gz : 0];
             v[m] = in ? x : 0.0;
         }
 #pragma unroll
-        for (int m = 0; m < KU; ++m)
-            if (tid + m * NT < R::NU)
-                su[tid + m * NT] = v[m];
+        for (int m = 0; m < PU; ++m)
+            if (grp < GU && lz0 + m < RU)
+                su[lx + UX * (ly + RU * (lz0 + m))] = v[m];
     }
     // right-hand side of the fine interior nodes of the footprint (origin
-    // ux0 + 1), loaded while the block waits at the barrier
-    double fv[KR];
+    // ux0 + 1), for the planes of this thread's residual column, loaded while
+    // the block waits at the barrier
+    const int rcol = tid % CR2, rgrp = tid / CR2;
+    const int rx = rcol % RR, ry = rcol / RR, rz0 = rgrp * PR;
+    const int hx = ux0 + 1 + rx, hy = uy0 + 1 + ry;
+    const bool rcin = rgrp < GR && hx >= 1 && hx <= nf - 1 && hy >= 1 && hy <= nf - 1;
+    const long rco = hx + fy * hy;
+    double fv[PR];
 #pragma unroll
-    for (int m = 0; m < KR; ++m) {
-        const int el = tid + m * NT;
-        const int lz = el / (RR * RR), rem = el - lz * (RR * RR);
-        const int ly = rem / RR, lx = rem - ly * RR;
-        const int gx = ux0 + 1 + lx, gy = uy0 + 1 + ly, gz = uz0 + 1 + lz;
-        const bool in = el < R::NR && gx >= 1 && gx <= nf - 1 && gy >= 1 && gy <= nf - 1 &&
-                        gz >= 1 && gz <= nf - 1;
-        fv[m] = F[in ? gx + fy * gy + fz * gz : 0];
+    for (int m = 0; m < PR; ++m) {
+        const int gz = uz0 + 1 + rz0 + m;
+        const bool in = rcin && rz0 + m < RR && gz >= 1 && gz <= nf - 1;
+        fv[m] = F[in ? rco + fz * gz : 0];
     }
     lds_barrier();
-    // r on the fine interior nodes of the footprint
+    // r on the fine interior nodes of the footprint, walking the column up
+    // its planes with the 3 x 3 neighbourhoods of three consecutive planes
+    // in registers (the residual's expression is that of resid_val)
+    if (rgrp < GR && rz0 < RR) {
+        const double *cb = static_cast<const double *>(su) + (rx + 1) + UX * (ry + 1);
+        auto win = [&](double *W, int pz) {
+            const double *b = cb + UX * RU * pz;
 #pragma unroll
-    for (int m = 0; m < KR; ++m) {
-        const int el = tid + m * NT;
-        if (el >= R::NR)
-            break;
-        const int lz = el / (RR * RR), rem = el - lz * (RR * RR);
-        const int ly = rem / RR, lx = rem - ly * RR;
-        const int gx = ux0 + 1 + lx, gy = uy0 + 1 + ly, gz = uz0 + 1 + lz;
-        double rv = 0.0;
-        if (gx >= 1 && gx <= nf - 1 && gy >= 1 && gy <= nf - 1 && gz >= 1 && gz <= nf - 1) {
-            const long pu = (lx + 1) + RU * (ly + 1) + long(RU * RU) * (lz + 1);
-            rv = resid_val<OP>(static_cast<const double *>(su), pu, RU, RU * RU, G.s, fv[m]);
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx)
+                    W[(dy + 1) * 3 + (dx + 1)] = b[dx + UX * dy];
+        };
+        double P0[9], P1[9], P2[9];
+        win(P0, rz0);
+        win(P1, rz0 + 1);
+#pragma unroll
+        for (int m = 0; m < PR; ++m) {
+            const int lz = rz0 + m;
+            if (lz >= RR)
+                break;
+            win(P2, lz + 2);
+            const int gz = uz0 + 1 + lz;
+            double rv = 0.0;
+            if (rcin && gz >= 1 && gz <= nf - 1)
+                rv = resid_win<OP>(P0 + 4, P1 + 4, P2 + 4, G.s, fv[m]);
+            sr[rx + RX * (ry + RR * lz)] = rv;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                P0[q] = P1[q];
+                P1[q] = P2[q];
+            }
         }
-        sr[el] = rv;
     }
     lds_barrier();
     const long cy = nc + 1, cz = cy * cy;
@@ -874,16 +904,16 @@ __global__ __launch_bounds__(NT) void k_rrestrict(const RrList *__restrict__ Lst
         const int I = I0 + a, J = J0 + b2 % TC, K = K0 + b2 / TC;
         if (I > nc || J > nc || K > nc)
             continue;
-        const long fu = (2 * I - ux0) + RU * (2 * J - uy0) + long(RU * RU) * (2 * K - uz0);
-        const long fr = (2 * I - ux0 - 1) + RR * (2 * J - uy0 - 1) + long(RR * RR) * (2 * K - uz0 - 1);
+        const long fu = (2 * I - ux0) + UX * (2 * J - uy0) + long(UX * RU) * (2 * K - uz0);
+        const long fr = (2 * I - ux0 - 1) + RX * (2 * J - uy0 - 1) + long(RX * RR) * (2 * K - uz0 - 1);
         const long c = I + cy * J + cz * K;
         const double v = su[fu];
         wc[c] = v;
         uc[c] = v;
         double bv = 0.0;
         if (I >= 1 && I <= nc - 1 && J >= 1 && J <= nc - 1 && K >= 1 && K <= nc - 1)
-            bv = restrict_b<OP, RMODE>(static_cast<const double *>(su), fu, RU, RU * RU,
-                                       static_cast<const double *>(sr), fr, RR, RR * RR, sc);
+            bv = restrict_b<OP, RMODE>(static_cast<const double *>(su), fu, UX, UX * RU,
+                                       static_cast<const double *>(sr), fr, RX, RX * RR, sc);
         bc[c] = bv;
     }
 }
