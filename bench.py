@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # known size): profiles/k_batched_sweep_quadratic129_counters.md.  Valid for
 # the k_batched sweep kernel as profiled; reset to None when it changes.
 SERVE_RATE = 30.0   # served stream: Poisson arrivals per second
-TRAFFIC = {("quadratic129", "fp64"): 31595418}
+TRAFFIC = {("quadratic129", "fp64"): 31601357}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
