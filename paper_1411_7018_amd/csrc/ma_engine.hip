@@ -780,10 +780,9 @@ template <int TC>
 struct RrShape {
     static constexpr int RU = 2 * TC + 3;    // u footprint per side (fine nodes)
     static constexpr int RR = 2 * TC + 1;    // r footprint per side
-    static constexpr int NU = RU * RU * RU, NR = RR * RR * RR;
     // LDS row strides, padded to 4 mod 8 doubles: the restriction reads the
-    // footprints at x stride 2, and with rows of 4 mod 8 doubles the 4 x 4
-    // coarse nodes of a plane fall on distinct bank pairs
+    // footprints at x stride 2, and rows of 4 mod 8 doubles spread the 4 x 4
+    // coarse nodes of a plane over more LDS banks than rows of 11 or 9
     static constexpr int UX = RU + (12 - RU % 8) % 8, RX = RR + (12 - RR % 8) % 8;
     static constexpr int SU = UX * RU * RU, SR = RX * RR * RR;   // LDS doubles
 };
