@@ -5,7 +5,8 @@ cut into launches:
   * ``max_blocks`` -- the cap on the blocks of one row-kernel launch.  Few
     blocks walk many rows each inside one XCD's window (good L2 reuse of the
     stencil halos on big grids); many blocks put more waves in flight (good
-    latency hiding on mid-size grids).
+    latency hiding).  The largest caps give the 385^3 finest level one row
+    per block.
   * ``coarse_n``   -- levels with n <= coarse_n run inside the
     single-workgroup coarse-level kernel instead of one launch per phase.
   * ``strip_rows`` -- the width of the y-strips in which a launch walks its
@@ -30,7 +31,7 @@ import time
 
 import torch
 
-BLOCKS = (4096, 8192, 16384, 32768, 65536)
+BLOCKS = (4096, 8192, 16384, 32768, 65536, 131072, 262144)
 COARSE = (0, 8, 16, 32)
 STRIPS = (8, 32, 128, 4096)
 BLOCK_N = (-1, 32, 64)
