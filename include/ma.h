@@ -95,9 +95,9 @@ typedef struct {
     int init_max_cycles;   /* cap on the linear V-cycles of MA_INIT_POISSON      */
     int inner_cycles;      /* MA_MIXED: FP32 V-cycles per outer correction       */
     int profile;           /* 1: time finest-level smoothing with HIP events     */
-    int tile_config;       /* block sweep shape: 0 automatic, 1..5 fixed (8^3
+    int tile_config;       /* block sweep shape: 0 automatic, 1..7 fixed (8^3
                               blocks of 256, 512, 1024 threads; 16x8x4 of 256;
-                              16x16x8 of 512)                                    */
+                              16x16x8 of 512; 8x8x4 of 512, 256)                 */
     int block_n;           /* MA_SMOOTHER_AUTO: block sweeps on levels with
                               n <= block_n; 0 automatic (64), -1 never          */
     int graphs;            /* 1: replay each cycle from a captured hipGraph      */

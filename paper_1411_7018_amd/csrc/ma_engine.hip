@@ -1846,14 +1846,17 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
         for (int d = 0; d < D_; ++d) {
             bool blk = !mixed;
             int nmax = 0;
+            long tiles8 = 0;
             for (int i = 0; i < S && blk; ++i) {
                 if (!solves_[i].s || multiblock_levels(i) <= d)
                     continue;
                 const int n = solves_[i].s->lv[d].n;
                 blk = block_level(n);
                 nmax = std::max(nmax, n);
+                const long t = (n - 1 + 7) / 8;
+                tiles8 += t * t * t;
             }
-            const int cfg = tile_config_ > 0 ? tile_config_ - 1 : bsweep_pick(nmax);
+            const int cfg = tile_config_ > 0 ? tile_config_ - 1 : bsweep_pick(nmax, tiles8);
             auto has = [&](int i) { return solves_[i].s && multiblock_levels(i) > d; };
             auto pairs = [&](int nsw, auto count, std::vector<int> &out) {
                 out.assign(nsw, -1);

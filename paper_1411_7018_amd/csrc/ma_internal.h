@@ -31,7 +31,9 @@ hipError_t launch_sweep_color(hipStream_t st, int op, int order, int n, double *
 hipError_t launch_bsweep_one(hipStream_t st, int op, int cfg, int n, const double *u_in,
                              double *u_out, const double *F, unsigned long long *nonconvex);
 int bsweep_num_configs();
-int bsweep_pick(int n);
+// Automatic block shape for grids of up to n intervals whose 8^3 tiles number
+// tiles8 in all.
+int bsweep_pick(int n, long tiles8);
 
 // --- residual and norm ----------------------------------------------------
 // r = F - S(u) (interior; 0 on the boundary; r may be null) and per-block sums

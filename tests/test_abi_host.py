@@ -78,7 +78,7 @@ def test_create_rejects_invalid_params_without_gpu():
     from paper_1411_7018_amd import _lib as L
     for field, val in (("n", 1), ("nu0", 0), ("order", 7), ("precision", 9),
                        ("restriction", 5), ("inner_cycles", 0), ("smoother", 3),
-                       ("tile_config", 6), ("tile_config", -1), ("block_n", -2),
+                       ("tile_config", 8), ("tile_config", -1), ("block_n", -2),
                        ("coarse_n", 33), ("max_blocks", 12), ("strip_rows", 5000)):
         p = L.ma_params_default(16)
         setattr(p, field, val)
@@ -99,7 +99,7 @@ def test_launch_shape_defaults():
     for bn in (-1, 0, 32, 2048):
         p.block_n = bn
         assert L.ma_footprint_bytes(p) > 0
-    for tc in range(0, 6):
+    for tc in range(0, 8):
         p.block_n, p.tile_config = 0, tc
         assert L.ma_footprint_bytes(p) > 0
     p.block_n = 2049

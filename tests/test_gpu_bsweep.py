@@ -47,7 +47,7 @@ def start(p, seed):
 
 
 # ragged grids (n - 1 not a multiple of the block sides) and tiny ones
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("n", [4, 9, 33, 47, 64, 100])
 def test_block_sweep_bitwise_vs_color_and_oracle(n, cfg):
     note("block sweep", n, cfg)
