@@ -151,7 +151,15 @@ double mao_local_root(const double *g, double F)
     const double q = F - detB;        /* y^3 + p y + q = 0 with p = -P */
     double y;
     const double D = 0.25 * q * q - P * P * P / 27.0;
-    if (P <= 0.0 || D >= 0.0) {
+    /* F > 0 and q < 0: by Theorem 2.2 a root lies below lambda_min <= m, i.e.
+     * y < 0, while Cardano's single real root would be positive, so the
+     * cubic has three real roots and D < 0.  With a double smallest
+     * eigenvalue D is within rounding of 0 and can come out >= 0, where
+     * Cardano would return the largest root: such a D is taken as the
+     * three-root case. */
+    const int near_double = F > 0.0 && P > 0.0 && q < 0.0 && D >= 0.0
+                            && D <= 1e-10 * (P * P * P / 27.0);
+    if ((P <= 0.0 || D >= 0.0) && !near_double) {
         /* one real root (or a multiple root): Cardano without cancellation */
         const double sq = sqrt(D > 0.0 ? D : 0.0);
         const double A = -copysign(cbrt(0.5 * fabs(q) + sq), q);

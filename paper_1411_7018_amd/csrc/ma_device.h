@@ -103,7 +103,8 @@ __device__ __forceinline__ void shifted_cubic(const Hess &g, double F, double si
 }
 
 // General smallest real root of det(G - sig I) = F, used only off the
-// convex branch (F <= 0 or a failed Newton bracket).  With m = tr G / 3 and
+// convex branch (F <= 0, a Newton iteration that did not settle, or a
+// non-finite result).  With m = tr G / 3 and
 // y = sig - m the cubic is y^3 - P y + (F - det(G - m I)) = 0, P = tr(B^2)/2
 // for the traceless B = G - m I.  Writing y = 2 t cos(phi), t = sqrt(P/3),
 // gives cos(3 phi) = -(F - det B)/(2 t^3); the smallest of the three real
@@ -122,8 +123,13 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
     if (P > 0.0) {
         const double t = sqrt(P * (1.0 / 3.0));
         const double arg = -0.5 * Q / (t * t * t);
-        if (arg >= -1.0 && arg <= 1.0) {
-            y = 2.0 * t * cos((acos(arg) + 2.0 * M_PI) * (1.0 / 3.0));
+        // F > 0 with a double smallest eigenvalue puts arg just below 1
+        // (three real roots, the lower two close); rounding can push it past
+        // 1, where the hyperbolic form would return the largest root, so a
+        // rounding-sized excess is read as 1.
+        const bool near_double = F > 0.0 && arg > 1.0 && arg <= 1.0 + 1e-10;
+        if ((arg >= -1.0 && arg <= 1.0) || near_double) {
+            y = 2.0 * t * cos((acos(fmin(arg, 1.0)) + 2.0 * M_PI) * (1.0 / 3.0));
         } else if (arg > 1.0) {
             y = 2.0 * t * cosh(acosh(arg) * (1.0 / 3.0));
         } else {
@@ -161,11 +167,16 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
 // The Newton quotient uses the hardware reciprocal refined by one
 // Newton-Raphson step (relative error ~1e-16); an inexact quotient only
 // perturbs the iteration, not its limit.  Stop when the step is below 1e-9 of
-// the eigenvalue scale: the error after that step is O(step^2 / scale), i.e.
-// at round-off.
+// the eigenvalue scale AND below 1e-3 of the previous step: in the quadratic
+// phase the error after such a step is O(step^2 / scale), i.e. at round-off.
+// Near a double smallest eigenvalue with tiny F the iteration converges only
+// linearly (steps halve), and a small step says nothing about the remaining
+// error; the ratio test keeps it going until the root separates, and a node
+// that has not settled after 64 steps is not trusted.
 //
-// nonconvex is set when F <= 0 or the result is not finite; such nodes take
-// the general closed form.
+// nonconvex is set when F <= 0, when Newton does not settle within 64
+// steps, or when the result is not finite; such nodes take the general
+// closed form.
 __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &nonconvex)
 {
     const double mab = g.xx * g.yy - g.xy * g.xy;
@@ -185,6 +196,8 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
     }
     const double c0 = I3 - F;
     const double thr = 1e-9 * (fabs(I1) + fabs(sig));
+    double dprev = INFINITY;
+    bool settled = false;
     for (int it = 0; it < 64; ++it) {
         const double q = ((I1 - sig) * sig - I2) * sig + c0;
         const double dq = (2.0 * I1 - 3.0 * sig) * sig - I2;
@@ -192,10 +205,14 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         r = fma(r, fma(-dq, r, 1.0), r);
         const double d = q * r;
         sig -= d;
-        if (!(fabs(d) > thr))
+        const double ad = fabs(d);
+        if (!(ad > thr) && !(ad > 1e-3 * dprev)) {
+            settled = true;
             break;
+        }
+        dprev = ad;
     }
-    if (!isfinite(sig)) {
+    if (!settled || !isfinite(sig)) {
         nonconvex = true;
         return smallest_root_general(g, F);
     }

@@ -35,12 +35,26 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import threading
 import time
 
 import numpy as np
 
+# ma_status values (include/ma.h)
 MA_ERR_OOM = 2
+MA_ERR_NOT_CONVERGED = 4
+MA_ERR_NONFINITE = 5
+
+
+def failure_status(report) -> int:
+    """Status of a solve that left the batch with an error (ma_batch_tick
+    marks it 2): a residual norm that is not finite, else the cycle limit.
+    Distinct from MA_ERR_OOM, which the server gives to rejected requests."""
+    res = (report or {}).get("res")
+    if res is not None and not math.isfinite(res):
+        return MA_ERR_NONFINITE
+    return MA_ERR_NOT_CONVERGED
 
 
 @dataclasses.dataclass
@@ -244,7 +258,7 @@ class Server:
                     for slot, code in done.items():
                         req, solver, u, f = self._live.pop(slot)
                         req.report = self.batch.report(slot)
-                        req.status = 0 if code == 1 else int(code)
+                        req.status = 0 if code == 1 else failure_status(req.report)
                         req.t_done = tnow
                         if self.keep_results:
                             req.u = u
@@ -369,7 +383,7 @@ class Server:
                         for slot, code in done.items():
                             req, solver, u, f = live.pop(slot)
                             req.report = batch.report(slot)
-                            req.status = 0 if code == 1 else int(code)
+                            req.status = 0 if code == 1 else failure_status(req.report)
                             req.t_done = tnow
                             if self.keep_results:
                                 req.u = u

@@ -1,0 +1,85 @@
+"""The local root rule on the GPU where Newton converges slowly: a double
+(or nearly double) smallest eigenvalue of the discrete Hessian with tiny F
+(eqs. 2.8-2.9, Theorem 2.2: the wanted root is the one below lambda_min).
+
+On a 3^3 grid (one unknown, h = 1/2) the data u = x^T M x / 2 makes the
+discrete Hessian at the centre M itself, so one sweep solves
+det(M - sigma I) = F there and moves the centre by sigma h^2 / 2.  Near a
+double root the cubic is flat to second order and any FP64 evaluation fixes
+the root only to ~sqrt(eps), hence the 3e-8 tolerance against the oracle's
+closed form.  Newton from the left converges only linearly there (steps
+halve); the GPU rule keeps iterating until a step is both small and far
+smaller than the one before, which here happens at FP64's noise floor,
+i.e. within that same sqrt(eps).  (A node that has not settled after 64
+steps would be recomputed by the closed form and counted as
+non-certified.)"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_7018_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _quadratic(M):
+    x, y, z = P.grid(2)
+    pts = np.stack([x, y, z], axis=-1)
+    return 0.5 * np.einsum("...a,ab,...b->...", pts, M, pts)
+
+
+def _sigma_pair(M, F):
+    from paper_1411_7018_amd import Solver
+    u0 = _quadratic(M)
+    f = np.full_like(u0, F)
+    want = u0.copy()
+    oracle.sweep(want, f, "4c")
+    u = torch.from_numpy(u0.copy()).cuda()
+    count = Solver(2).sweep(u, torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    # sigma = (new - old) / (h^2 / 2), h^2 / 2 = 1/8
+    return 8.0 * (got[1, 1, 1] - u0[1, 1, 1]), 8.0 * (want[1, 1, 1] - u0[1, 1, 1]), count
+
+
+@pytest.mark.parametrize("F", [1e-300, 1e-30])
+def test_exact_double_eigenvalue_takes_smallest_root(F):
+    print("[case] root exact double", F, file=sys.stderr, flush=True)
+    M = np.diag([1.0, 1.0, 2.0])
+    sg, so, count = _sigma_pair(M, F)
+    assert count in (0, 1)
+    assert sg <= 1.0 + 1e-12 and so <= 1.0 + 1e-12
+    assert abs(sg - so) <= 3e-8
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_near_double_eigenvalue_rotated(seed):
+    print("[case] root near double", seed, file=sys.stderr, flush=True)
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    M = (q * np.array([0.75, 0.75 * (1 + 1e-13), 1.5])[None, :]) @ q.T
+    M = 0.5 * (M + M.T)
+    sg, so, _ = _sigma_pair(M, 1e-24)
+    lmin = np.linalg.eigvalsh(M)[0]
+    assert sg <= lmin + 3e-8
+    assert abs(sg - so) <= 3e-8
+
+
+def test_regular_node_unchanged_and_not_counted():
+    rng = np.random.default_rng(9)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    M = (q * np.array([0.6, 1.1, 1.9])[None, :]) @ q.T
+    M = 0.5 * (M + M.T)
+    sg, so, count = _sigma_pair(M, 0.9 * np.linalg.det(M))
+    assert count == 0
+    assert abs(sg - so) <= 1e-12

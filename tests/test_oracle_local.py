@@ -163,3 +163,32 @@ def test_single_unknown_grid_matches_expanded_cubic():
         mask = np.ones_like(u, bool)
         mask[1, 1, 1] = False
         assert np.array_equal(v[mask], u[mask])   # Dirichlet layer untouched
+
+
+def _bisect_double(l1, l3, F):
+    """Smallest root of (l1 - s)^2 (l3 - s) = F below l1 by bisection on the
+    product form (no cancellation)."""
+    lo, hi = l1 - 1.0 - abs(F) ** (1.0 / 3.0), l1
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (l1 - mid) ** 2 * (l3 - mid) - F > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("F", [1e-300, 1e-20, 1e-12, 1e-6])
+def test_root_double_smallest_eigenvalue_tiny_F(F):
+    """G = diag(1, 1, 2): a double smallest eigenvalue.  For F > 0 the cubic
+    has three real roots, the lower two within ~sqrt(F) of 1 (Theorem 2.2:
+    the wanted one lies below lambda_min).  Rounding hides the separation
+    of the lower pair from the discriminant, which must not turn the result
+    into the largest root (near 2).  Near a double root the cubic in its
+    expanded or shifted form is flat to second order, so rounding errors of
+    size eps in q move the root by ~sqrt(eps): the tolerance is 3e-8."""
+    g = np.array([1.0, 1.0, 2.0, 0.0, 0.0, 0.0])
+    want = _bisect_double(1.0, 2.0, F)
+    got = oracle.local_root(g, F)
+    assert got <= 1.0 + 1e-12
+    assert got == pytest.approx(want, abs=3e-8)

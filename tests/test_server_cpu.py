@@ -26,11 +26,12 @@ class FakeBatch:
         for s, v in self.live.items():
             v[0] -= 1
             if v[0] <= 0:
-                done[s] = 1
+                done[s] = 2 if v[1]["n"] in self.be.fail else 1
         return done
 
     def report(self, slot):
-        return {"cycles": self.be.ticks_for(self.live[slot][1]["n"])}
+        n = self.live[slot][1]["n"]
+        return {"cycles": self.be.ticks_for(n), "res": self.be.fail.get(n, 1e-9)}
 
     def remove(self, slot):
         del self.live[slot]
@@ -56,6 +57,7 @@ class FakeBackend:
         self.slots = slots
         self.max_concurrent = 0
         self.solvers_made = 0
+        self.fail = {}      # n -> final residual of a solve of that size that fails
 
     def hierarchy_bytes(self, n):
         return 5 * n ** 3
@@ -83,8 +85,9 @@ class FakeBackend:
         return batch.add(solver, u, f)
 
 
-def run(reqs, budget, slots=64, **kw):
+def run(reqs, budget, slots=64, fail=None, **kw):
     be = FakeBackend(slots)
+    be.fail = fail or {}
     srv = Server(be, budget, max_slots=slots, **kw)
     # wrap the memory accounting to check the budget after every admission
     orig = srv._try_admit
@@ -174,3 +177,15 @@ def test_stats_percentiles():
     lat = sorted(r.latency for r in reqs)
     assert st.p50 == pytest.approx(lat[24] / 2 + lat[25] / 2)
     assert st.p99 >= st.p50 > 0 and st.solves_per_s > 0
+
+
+def test_failed_solves_keep_their_own_status():
+    """A solve that stops with an error is reported as not converged or
+    non-finite, never as the rejection status of admission."""
+    from paper_1411_7018_amd.server import (MA_ERR_NONFINITE, MA_ERR_NOT_CONVERGED,
+                                            MA_ERR_OOM)
+    reqs = trace([16, 32, 48, 16, 128], gap=0.001)
+    st, srv, be = run(reqs, budget=7 * 64 ** 3, fail={32: 3.0, 48: float("nan")})
+    assert [r.status for r in reqs] == [0, MA_ERR_NOT_CONVERGED, MA_ERR_NONFINITE, 0,
+                                       MA_ERR_OOM]
+    assert st.completed == 2 and st.rejected == 1
