@@ -72,3 +72,60 @@ def test_served_results_equal_solo(precision, tight, lanes):
         assert r.status == 0
         want = solo(r.kind, r.n, r.seed, precision)
         assert np.array_equal(r.u.cpu().numpy(), want), (r.rid, r.kind, r.n)
+
+
+def oracle_trace():
+    """Requests of the served stream's smaller sizes (65^3, 129^3) beside
+    small ones, arriving while others cycle."""
+    sizes = [64, 32, 128, 64, 16, 64]
+    kinds = ["exp_cos", "quadratic", "exp_cos", "quadratic", "exp_cos", "exp_cos"]
+    return [(0.003 * i, kinds[i], sizes[i], 5100 + i) for i in range(len(sizes))]
+
+
+@pytest.mark.parametrize("lanes", [None, [[16, 32, 64], [128]]])
+def test_served_fp64_results_match_oracle(lanes):
+    """Each served FP64 result equals the oracle's solve of the same data
+    (Poisson guess, FAS V(2,2) to 1e-8) at the same cycle count, to 1e-12."""
+    import oracle
+    from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
+    note("server vs oracle fp64", "lanes" if lanes else "one batch")
+    be = GpuBackend(precision="fp64", tol=1e-8, max_slots=8)
+    reqs = requests_from_trace(oracle_trace())
+    srv = Server(be, 8 << 30, max_slots=8, keep_results=True, lanes=lanes)
+    st = srv.run(reqs)
+    assert st.completed == len(reqs) and st.max_live > 1
+    for r in reqs:
+        u0, f = P.make_device(r.kind, r.n, r.seed)
+        torch.cuda.synchronize()
+        want = u0.cpu().numpy()
+        ost, orep, _ = oracle.solve(want, f.cpu().numpy(), oracle.params(tol=1e-8))
+        assert ost == 0
+        assert r.status == 0 and r.report["cycles"] == orep.cycles, (r.rid, r.n)
+        got = r.u.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (r.rid, r.kind, r.n)
+
+
+@pytest.mark.parametrize("tol,bound", [(1e-10, 1e-10), (1e-8, 1e-8)])
+def test_served_mixed_results_match_oracle_limit(tol, bound):
+    """Each served mixed-precision result against the oracle's converged
+    discrete solution (run to its round-off floor): <= 1e-10 in the max norm
+    when the stream runs to 1e-10; at the 1e-8 stop the remaining solver
+    error is of order ||L^-1|| * 1e-8 and the agreement reached is printed."""
+    import oracle
+    from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
+    note("server vs oracle limit mixed", tol)
+    be = GpuBackend(precision="mixed", tol=tol, max_slots=8)
+    reqs = requests_from_trace([x for x in oracle_trace() if x[2] <= 64])
+    srv = Server(be, 8 << 30, max_slots=8, keep_results=True)
+    st = srv.run(reqs)
+    assert st.completed == len(reqs)
+    worst = 0.0
+    for r in reqs:
+        u0, f = P.make_device(r.kind, r.n, r.seed)
+        torch.cuda.synchronize()
+        lim = u0.cpu().numpy()
+        oracle.solve_limit(lim, f.cpu().numpy())
+        d = float(np.abs(r.u.cpu().numpy() - lim).max())
+        worst = max(worst, d)
+        assert r.status == 0 and d <= bound, (r.rid, r.kind, r.n, d)
+    note(f"served mixed at tol {tol:g}: max|u - oracle limit| = {worst:.3e}")
