@@ -97,7 +97,9 @@ typedef struct {
     int profile;           /* 1: time finest-level smoothing with HIP events     */
     int tile_config;       /* block sweep shape: 0 automatic, 1..7 fixed (8^3
                               blocks of 256, 512, 1024 threads; 16x8x4 of 256;
-                              16x16x8 of 512; 8x8x4 of 512, 256)                 */
+                              16x16x8 of 512; 8x8x4 of 512, 256); 8..11 the
+                              z-stream sweep's columns (32x26 of 1024, 512
+                              threads, 32x26 with twice the chunks, 40x20)     */
     int block_n;           /* MA_SMOOTHER_AUTO: block sweeps on levels with
                               n <= block_n; 0 automatic (64), -1 never          */
     int graphs;            /* 1: replay each cycle from a captured hipGraph      */
@@ -107,6 +109,11 @@ typedef struct {
                               of 8, 0 automatic = 16384)                         */
     int strip_rows;        /* x-rows per y-strip in the work order of a batched
                               launch (strips are walked along z; 0 automatic)    */
+    int zsweep_n;          /* MA_SMOOTHER_AUTO, 4-colour FP64: z-stream sweeps
+                              (all four colour phases of a sweep in one launch,
+                              each workgroup walking a column of the grid plane
+                              by plane, out of place) on levels with
+                              n >= zsweep_n; 0 automatic, -1 never              */
 } ma_params;
 
 typedef struct {
@@ -170,6 +177,10 @@ ma_status ma_set_stream(ma_solver *s, void *hip_stream);
  * every value.  Errors: MA_ERR_ARG for values outside their ranges (nothing
  * changes). */
 ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows, int block_n);
+
+/* The same for the smoother's shape: block_n, zsweep_n and tile_config as in
+ * ma_params.  Results are unchanged by every value. */
+ma_status ma_retune_smoother(ma_solver *s, int block_n, int zsweep_n, int tile_config);
 
 /* Solve det(D^2 u) = f (Algorithm 1 repeated under the stopping rule of
  * Section 4): run V(nu1,nu2) cycles until the discrete L2 residual is

@@ -35,7 +35,8 @@ class ma_params(ctypes.Structure):
                 ("inner_cycles", ctypes.c_int), ("profile", ctypes.c_int),
                 ("tile_config", ctypes.c_int), ("block_n", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("coarse_n", ctypes.c_int),
-                ("max_blocks", ctypes.c_int), ("strip_rows", ctypes.c_int)]
+                ("max_blocks", ctypes.c_int), ("strip_rows", ctypes.c_int),
+                ("zsweep_n", ctypes.c_int)]
 
 
 class ma2d_params(ctypes.Structure):
@@ -91,6 +92,7 @@ _L.ma_last_error.argtypes = [_vp]
 _L.ma_last_error.restype = ctypes.c_char_p
 _L.ma_set_stream.argtypes = [_vp, _vp]
 _L.ma_retune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_L.ma_retune_smoother.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _L.ma_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_vcycle.argtypes = [_vp, _vp, _vp]
 _L.ma_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
@@ -130,7 +132,8 @@ _L.ma2d_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
 for _name in ("ma2d_create", "ma2d_sweep", "ma2d_residual", "ma2d_vcycle", "ma2d_fmg",
               "ma2d_solve"):
     getattr(_L, _name).restype = ctypes.c_int
-for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
+for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_retune_smoother", "ma_solve",
+              "ma_vcycle",
               "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
               "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_add",
               "ma_batch_tick",
@@ -138,7 +141,8 @@ for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle"
     getattr(_L, _name).restype = ctypes.c_int
 
 EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", "ma_destroy",
-           "ma_last_error", "ma_set_stream", "ma_retune", "ma_solve", "ma_vcycle",
+           "ma_last_error", "ma_set_stream", "ma_retune", "ma_retune_smoother", "ma_solve",
+           "ma_vcycle",
            "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
            "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
            "ma_batch_last_error", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
@@ -196,6 +200,10 @@ def ma_set_stream(h: int, stream: int | None) -> None:
 
 def ma_retune(h: int, coarse_n: int, max_blocks: int, strip_rows: int, block_n: int = 0) -> None:
     _check(_L.ma_retune(h, int(coarse_n), int(max_blocks), int(strip_rows), int(block_n)), h)
+
+
+def ma_retune_smoother(h: int, block_n: int, zsweep_n: int, tile_config: int) -> None:
+    _check(_L.ma_retune_smoother(h, int(block_n), int(zsweep_n), int(tile_config)), h)
 
 
 def ma_solve(h: int, u: int, f: int, tol: float, flags: int) -> ma_report:

@@ -1,6 +1,10 @@
-// Launchers of the block sweep (ma_fsweep.h): the block shapes it is built
-// for and the automatic choice between them.
+// Launchers of the block sweep (ma_fsweep.h) and of the z-stream sweep
+// (ma_zsweep.h): the shapes they are built for and the automatic choice
+// between them.
 #include "ma_fsweep.h"
+#include "ma_zsweep.h"
+
+#include <algorithm>
 
 namespace mafas {
 
@@ -8,14 +12,36 @@ namespace {
 
 struct BCfg {
     int tx, ty, tz, nt;
+    int zwg;   // 0: block sweep; > 0: z-stream sweep aiming at about zwg workgroups
 };
-// Block shapes (index = tile_config - 1).  Small blocks keep the
+// Shapes (index = tile_config - 1).  Block sweeps: small blocks keep the
 // recomputation cheap in absolute terms and give many workgroups; more
 // threads per block cut the rounds of updates per phase, which is what a
-// sweep of a small grid waits on.
-constexpr BCfg kCfg[] = {{8, 8, 8, 256}, {8, 8, 8, 512},  {8, 8, 8, 1024}, {16, 8, 4, 256},
-                         {16, 16, 8, 512}, {8, 8, 4, 512}, {8, 8, 4, 256}};
+// sweep of a small grid waits on.  Z-stream sweeps (tz unused): TX x TY
+// columns whose update items (TX TY + 3 (TX + TY) + 14 per step) nearly
+// fill the workgroup once or twice; the planes are cut into chunks so that
+// a launch has about zwg workgroups (one per compute unit at a time, the
+// ring filling most of the LDS).
+constexpr BCfg kCfg[] = {{8, 8, 8, 256, 0},   {8, 8, 8, 512, 0},  {8, 8, 8, 1024, 0},
+                         {16, 8, 4, 256, 0},  {16, 16, 8, 512, 0}, {8, 8, 4, 512, 0},
+                         {8, 8, 4, 256, 0},   {32, 26, 0, 1024, 1536}, {32, 26, 0, 512, 1536},
+                         {32, 26, 0, 1024, 3072}, {40, 20, 0, 1024, 1536}};
 constexpr int kNumCfg = int(sizeof(kCfg) / sizeof(kCfg[0]));
+
+template <int OP, int TX, int TY, int NT>
+hipError_t zgo_list(hipStream_t st, const FsList *L, int blocks, unsigned long long *nc)
+{
+    hipLaunchKernelGGL((k_zsweep<OP, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, L, nc);
+    return hipGetLastError();
+}
+
+template <int OP, int TX, int TY, int NT>
+hipError_t zgo_one(hipStream_t st, const FsGrid &G, unsigned long long *nc)
+{
+    const int blocks = G.tiles_x * G.tiles_y * G.tiles_z;
+    hipLaunchKernelGGL((k_zsweep1<OP, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, G, nc);
+    return hipGetLastError();
+}
 
 template <int OP, int TX, int TY, int TZ, int NT>
 hipError_t go_list(hipStream_t st, const FsList *L, int blocks, unsigned long long *nc)
@@ -50,6 +76,13 @@ hipError_t list_op(int cfg, hipStream_t st, const FsList *L, int blocks, unsigne
         return go_list<OP, 8, 8, 4, 512>(st, L, blocks, nc);
     case 6:
         return go_list<OP, 8, 8, 4, 256>(st, L, blocks, nc);
+    case 7:
+    case 9:
+        return zgo_list<OP, 32, 26, 1024>(st, L, blocks, nc);
+    case 8:
+        return zgo_list<OP, 32, 26, 512>(st, L, blocks, nc);
+    case 10:
+        return zgo_list<OP, 40, 20, 1024>(st, L, blocks, nc);
     default:
         return hipErrorInvalidValue;
     }
@@ -73,6 +106,13 @@ hipError_t one_op(int cfg, hipStream_t st, const FsGrid &G, unsigned long long *
         return go_one<OP, 8, 8, 4, 512>(st, G, nc);
     case 6:
         return go_one<OP, 8, 8, 4, 256>(st, G, nc);
+    case 7:
+    case 9:
+        return zgo_one<OP, 32, 26, 1024>(st, G, nc);
+    case 8:
+        return zgo_one<OP, 32, 26, 512>(st, G, nc);
+    case 10:
+        return zgo_one<OP, 40, 20, 1024>(st, G, nc);
     default:
         return hipErrorInvalidValue;
     }
@@ -110,7 +150,16 @@ void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *
     G->n = n;
     G->tiles_x = (n - 1 + b.tx - 1) / b.tx;
     G->tiles_y = (n - 1 + b.ty - 1) / b.ty;
-    G->tiles_z = (n - 1 + b.tz - 1) / b.tz;
+    if (b.zwg > 0) {
+        // chunks of at least 16 planes, about zwg workgroups in all; the
+        // last chunk takes what remains (none is empty)
+        const int cols = G->tiles_x * G->tiles_y;
+        int chunks = std::max(1, std::min((n - 1) / 16, (b.zwg + cols - 1) / cols));
+        const int zc = zs_chunk(n, chunks);
+        G->tiles_z = (n - 1 + zc - 1) / zc;
+    } else {
+        G->tiles_z = (n - 1 + b.tz - 1) / b.tz;
+    }
     G->start = 0;
     G->slot = slot;
     G->s = double(n) * double(n);

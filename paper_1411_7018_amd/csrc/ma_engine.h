@@ -20,6 +20,11 @@
 namespace mafas {
 
 constexpr int kMaxGrids = 64;          // grids (solve, level) per batched launch
+// z-stream sweeps (ma_zsweep.h): first shape index among the block-sweep
+// configurations, and the smallest level that takes them when zsweep_n = 0
+constexpr int kZsFirstConfig = 7;
+constexpr int kZsweepAuto = 320;      // Monge-Ampere sweeps
+constexpr int kZsweepAutoLap = 192;   // linear sweeps of the Poisson guess
 constexpr int kDefaultMaxBlocks = 16384;
 constexpr int kTailThreads = 512;      // threads of the coarse-level kernel
 constexpr int kMaxTail = 6;            // levels per solve inside that kernel
@@ -290,9 +295,12 @@ class Engine {
     int Dall_ = 0;   // full depth of the active solves
     int nu1_ = 2, nu2_ = 2, nu0_ = 1, order_ = 0, rmode_ = 0, inner_ = 2;
     int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks, strip_rows_ = 0;
-    int smoother_ = MA_SMOOTHER_AUTO, tile_config_ = 0, block_n_ = 0;
+    int smoother_ = MA_SMOOTHER_AUTO, tile_config_ = 0, block_n_ = 0, zsweep_n_ = 0;
     int strip_width(int gy) const;
-    bool block_level(int n) const;     // sweeps of a multi-block n grid as block sweeps
+    // sweeps of a multi-block n grid as block sweeps, and among them as
+    // z-stream sweeps (the mode sets the automatic choice)
+    bool block_level(int n, Mode mode) const;
+    bool zs_level(int n, Mode mode) const;
 
     std::vector<char> hbuf_;               // host copy of the lists and the tail table
     std::vector<size_t> loff_;             // byte offset of each list

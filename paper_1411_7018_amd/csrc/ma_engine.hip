@@ -1367,11 +1367,11 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
                  p.inner_cycles != p0->inner_cycles || p.coarse_n != p0->coarse_n ||
                  p.max_blocks != p0->max_blocks || p.strip_rows != p0->strip_rows ||
                  p.smoother != p0->smoother || p.tile_config != p0->tile_config ||
-                 p.block_n != p0->block_n)
+                 p.block_n != p0->block_n || p.zsweep_n != p0->zsweep_n)
             return fail(MA_ERR_ARG,
                         "solvers in one batch must share smoothing counts, ordering, "
                         "restriction, precision, inner cycles, coarse_n, max_blocks, "
-                        "strip_rows, smoother, tile_config and block_n");
+                        "strip_rows, smoother, tile_config, block_n and zsweep_n");
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
@@ -1401,6 +1401,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     smoother_ = p0->smoother;
     tile_config_ = p0->tile_config;
     block_n_ = p0->block_n;
+    zsweep_n_ = p0->zsweep_n;
     built_ = false;
     if (!stream_) {
         E_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
@@ -1530,14 +1531,29 @@ int Engine::strip_width(int gy) const
 
 // Block sweeps for a multi-block level of n intervals (4-colour FP64 only;
 // the caller excludes MODE_MIXED).
-bool Engine::block_level(int n) const
+bool Engine::block_level(int n, Mode mode) const
 {
     if (order_ != MA_COLOR4 || smoother_ == MA_SMOOTHER_COLOR)
         return false;
-    if (smoother_ == MA_SMOOTHER_FUSED)
+    if (smoother_ == MA_SMOOTHER_FUSED || zs_level(n, mode))
         return true;
     const int lim = block_n_ == 0 ? 64 : block_n_;
     return n <= lim;
+}
+
+// Automatic choice (zsweep_n = 0), from whole-solve timings on MI355X: the
+// z-stream sweep moves each node once per sweep but recomputes ~23% of the
+// updates and waits on its barriers, so it pays where the colour launches
+// are bound by their traffic and the update is cheap -- the linear
+// Poisson sweeps from n = 192 (about 150 against 200 us per sweep at
+// 257^3), the Monge-Ampere sweeps only from n = 320 (about 770 against 800
+// us per sweep at 385^3; slower at 257^3).
+bool Engine::zs_level(int n, Mode mode) const
+{
+    if (order_ != MA_COLOR4 || smoother_ != MA_SMOOTHER_AUTO)
+        return false;
+    const int lim = zsweep_n_ != 0 ? zsweep_n_ : (mode == MODE_LAP ? kZsweepAutoLap : kZsweepAuto);
+    return lim > 0 && n >= lim;
 }
 
 int Engine::multiblock_levels(int i) const
@@ -1851,12 +1867,23 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                 if (!solves_[i].s || multiblock_levels(i) <= d)
                     continue;
                 const int n = solves_[i].s->lv[d].n;
-                blk = block_level(n);
+                blk = block_level(n, mode);
                 nmax = std::max(nmax, n);
                 const long t = (n - 1 + 7) / 8;
                 tiles8 += t * t * t;
             }
-            const int cfg = tile_config_ > 0 ? tile_config_ - 1 : bsweep_pick(nmax, tiles8);
+            // z-stream levels take a z-stream shape (tile_config 8..11, else
+            // the first), the others a block shape (tile_config 1..7, else
+            // the automatic pick)
+            const bool zs = zs_level(nmax, mode) ||
+                            (smoother_ == MA_SMOOTHER_FUSED && tile_config_ > kZsFirstConfig);
+            int cfg;
+            if (zs)
+                cfg = tile_config_ >= kZsFirstConfig + 1 ? tile_config_ - 1 : kZsFirstConfig;
+            else if (tile_config_ > 0 && tile_config_ <= kZsFirstConfig)
+                cfg = tile_config_ - 1;
+            else
+                cfg = bsweep_pick(nmax, tiles8);
             auto has = [&](int i) { return solves_[i].s && multiblock_levels(i) > d; };
             auto pairs = [&](int nsw, auto count, std::vector<int> &out) {
                 out.assign(nsw, -1);

@@ -52,7 +52,7 @@ bool valid_params(const ma_params *p, std::string &why)
     }
     if (p->tile_config < 0 || p->tile_config > bsweep_num_configs() || p->block_n < -1 ||
         p->block_n > 2048) {
-        why = "tile_config must be in 0..7 and block_n in -1..2048";
+        why = "tile_config must be in 0..11 and block_n in -1..2048";
         return false;
     }
     if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1 ||
@@ -70,6 +70,10 @@ bool valid_params(const ma_params *p, std::string &why)
     }
     if (p->strip_rows < 0 || p->strip_rows > 4096) {
         why = "strip_rows must be in 0..4096";
+        return false;
+    }
+    if (p->zsweep_n < -1 || p->zsweep_n > 2048) {
+        why = "zsweep_n must be in -1..2048";
         return false;
     }
     if (p->graphs != 0 && p->graphs != 1) {
@@ -211,6 +215,21 @@ ma_status ma_retune(ma_solver *s, int coarse_n, int max_blocks, int strip_rows, 
     q.max_blocks = max_blocks;
     q.strip_rows = strip_rows;
     q.block_n = block_n;
+    std::string why;
+    if (!valid_params(&q, why))
+        return s->fail(MA_ERR_ARG, why);
+    s->p = q;
+    return MA_OK;
+}
+
+ma_status ma_retune_smoother(ma_solver *s, int block_n, int zsweep_n, int tile_config)
+{
+    if (!s)
+        return MA_ERR_ARG;
+    ma_params q = s->p;
+    q.block_n = block_n;
+    q.zsweep_n = zsweep_n;
+    q.tile_config = tile_config;
     std::string why;
     if (!valid_params(&q, why))
         return s->fail(MA_ERR_ARG, why);
@@ -605,6 +624,8 @@ ma_solver *ma_solver::view(int l)
     views[l]->p.max_blocks = p.max_blocks;
     views[l]->p.strip_rows = p.strip_rows;
     views[l]->p.block_n = p.block_n;
+    views[l]->p.zsweep_n = p.zsweep_n;
+    views[l]->p.tile_config = p.tile_config;
     return views[l];
 }
 

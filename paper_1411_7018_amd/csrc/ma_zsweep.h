@@ -1,0 +1,334 @@
+// One complete 4-colour nonlinear Gauss-Seidel sweep per launch for large
+// grids, streamed along z: the z-stream sweep (Section 2: the pointwise
+// update of eqs. 2.7-2.9 applied colour by colour).
+//
+// The colour-phase kernels re-read the whole grid once per colour, since
+// the 19-point stencil of a node touches all three other colours; a sweep
+// then moves about twice its algorithmic bytes.  Here every node is read
+// and written once per sweep:
+//
+// * A workgroup owns a TX x TY column of output nodes and a chunk of planes
+//   [z0, z1).  It walks the chunk plane by plane with the colour phases
+//   skewed two planes apart: at step s it applies colour c to plane
+//   s - 2c, c = 0..3.  A colour-c node at plane P reads planes P-1..P+1;
+//   colour c-1 has finished those planes at earlier steps, colours above c
+//   reach them only at later steps, and the four updates of one step are at
+//   least two planes apart, so they are independent.  One workgroup
+//   barrier per step.
+// * The planes live in an LDS ring of 10 planes (9 are read at a step, one
+//   is being filled), each with a halo of 4 nodes in x and y, rows
+//   de-interleaved by x parity so a colour's nodes in a row are contiguous.
+//   The loads of plane s+4 are issued at the start of step s and written to
+//   LDS at the end of step s+2; a step is short next to the latency of HBM,
+//   and with loads one step ahead the walk waited on memory every step.
+// * Neighbouring columns update the same grid at the same time, so colour c
+//   is applied to the column grown by 3 - c nodes in x and y, and to the
+//   chunk grown by 3 - c planes in z: the recomputed halo needs only old
+//   values, which the sweep reads from u_in and never modifies (it writes
+//   u_out: out of place).
+// * Plane q is final after step q + 6 and is written to u_out at step
+//   q + 7 (owned nodes and the Dirichlet layer next to them).
+//
+// Each node's update is the same expression (hessian3 and the root rule of
+// ma_device.h) on the same values as in the colour-phase kernels, so the
+// result is bitwise identical to four colour phases.  Algorithmic bytes
+// per interior node and sweep: read u 8, read F 8, write u 8.
+#pragma once
+
+#include "ma_fsweep.h"
+
+#include <type_traits>
+
+namespace mafas {
+
+template <int TX, int TY>
+struct ZsShape {
+    static constexpr int H = 4;              // halo loaded around the column
+    static constexpr int LX = TX + 2 * H;    // LDS row length
+    static constexpr int LY = TY + 2 * H;    // LDS rows per plane
+    static constexpr int HW = LX / 2;        // one parity half of a row
+    static constexpr int PL = LX * LY;       // doubles per plane
+    static constexpr int R = 10;             // planes in the ring
+    static constexpr int NL = PL * R;        // doubles in LDS
+    // colour c covers TX/2 + e columns and TY/2 + e rows of its colour's
+    // nodes in a plane, e = 3 - c
+    static constexpr int ncol(int c) { return TX / 2 + 3 - c; }
+    static constexpr int nrow(int c) { return TY / 2 + 3 - c; }
+    static constexpr int count(int c) { return ncol(c) * nrow(c); }
+    // Update items: colours 0 and 1, then colours 2 and 3 from the next
+    // whole wavefront on.  A colour-c node at plane P has x parity
+    // (c >> 1) + P mod 2 and P has the step's parity, so the x parity -- and
+    // with it the LDS offsets of the x neighbours -- is the same across
+    // every wavefront.
+    static constexpr int first(int c)
+    {
+        return c == 0 ? 0
+               : c == 1 ? count(0)
+               : c == 2 ? (count(0) + count(1) + 63) / 64 * 64
+                        : (count(0) + count(1) + 63) / 64 * 64 + count(2);
+    }
+    static constexpr int items = first(3) + count(3);
+    static constexpr size_t lds_bytes() { return size_t(NL) * sizeof(double); }
+    static_assert(TX % 2 == 0 && TY % 2 == 0, "TX and TY must be even");
+};
+
+// Planes per chunk of an n grid cut into `chunks` chunks.
+__host__ __device__ inline int zs_chunk(int n, int chunks)
+{
+    return (n - 1 + chunks - 1) / chunks;
+}
+
+// Column `tile` of grid G by a workgroup of NT threads; su: LDS.  Global
+// offsets are 32-bit: grids up to n = 1289.
+template <int OP, int TX, int TY, int NT>
+__device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *__restrict__ su,
+                                            unsigned long long *__restrict__ ncount)
+{
+    using S = ZsShape<TX, TY>;
+    constexpr int LX = S::LX, HW = S::HW, PL = S::PL, H = S::H, R = S::R;
+    constexpr int KL = (PL + NT - 1) / NT;        // plane elements per thread
+    constexpr int MI = (S::items + NT - 1) / NT;  // update items per thread and step
+    constexpr int SX = TX + 2, SY = TY + 2;       // store bound (with Dirichlet layer)
+    constexpr int KS = (SX * SY + NT - 1) / NT;
+
+    const int n = G.n;
+    const int tid = int(threadIdx.x);
+    const int tx = tile % G.tiles_x;
+    const int rest = tile / G.tiles_x;
+    const int ty = rest % G.tiles_y;
+    const int tz = rest / G.tiles_y;
+    const int zc = zs_chunk(n, G.tiles_z);
+    const int x0 = 1 + tx * TX, y0 = 1 + ty * TY, z0 = 1 + tz * zc;
+    if (z0 > n - 1)
+        return;
+    const int x1 = min(x0 + TX, n), y1 = min(y0 + TY, n), z1 = min(z0 + zc, n);
+    const int lx0 = x0 - H, ly0 = y0 - H;
+    const int sy = n + 1, sz = sy * sy;
+    const auto uin = to_global(G.uin);
+    const auto uout = to_global(G.uout);
+    const auto F = to_global(G.F);
+
+    // ---- this thread's share of a plane load: global offset inside the
+    // plane (-1: outside the grid, LDS gets 0) and LDS offset inside a slot
+    int gofs[KL], lofs[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int el = tid + k * NT;
+        const int ly = el / LX, lx = el - (el / LX) * LX;
+        const int gx = lx0 + lx, gy = ly0 + ly;
+        const bool in = el < PL && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
+        gofs[k] = in ? gx + sy * gy : -1;
+        lofs[k] = el < PL ? ly * LX + (lx & 1) * HW + (lx >> 1) : -1;
+    }
+    auto slot = [&](int p) { return ((p + 2 * R) % R) * PL; };   // p >= -2R
+    auto fetch_plane = [&](int p, double *v) {
+        const bool pin = p >= 0 && p <= n;
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const bool in = pin && gofs[k] >= 0;
+            const double x = uin[in ? gofs[k] + sz * p : 0];
+            v[k] = in ? x : 0.0;
+        }
+    };
+    auto put_plane = [&](int p, const double *v) {
+        double *b = su + slot(p);
+#pragma unroll
+        for (int k = 0; k < KL; ++k)
+            if (lofs[k] >= 0)
+                b[lofs[k]] = v[k];
+    };
+
+    // ---- this thread's update items, fixed for the whole walk: colour
+    // (-1: none), the planes its colour covers, and for each parity of the
+    // step the node's offsets inside a plane (LDS and global), whether it
+    // lies in the grid interior and whether this column owns it.
+    int ic[MI], plo[MI], phi[MI], lio[MI][2], gio[MI][2];
+    bool okxy[MI][2], own[MI][2];
+#pragma unroll
+    for (int m = 0; m < MI; ++m) {
+        const int q = tid + m * NT;
+        int c = -1;
+        if (q < S::first(0) + S::count(0))
+            c = 0;
+        else if (q < S::first(1) + S::count(1))
+            c = 1;
+        else if (q >= S::first(2) && q < S::first(2) + S::count(2))
+            c = 2;
+        else if (q >= S::first(3) && q < S::first(3) + S::count(3))
+            c = 3;
+        const int cc = c < 0 ? 0 : c;
+        const int local = q - (cc == 0 ? S::first(0) : cc == 1 ? S::first(1)
+                               : cc == 2 ? S::first(2) : S::first(3));
+        const int e = 3 - cc, c0 = cc & 1, c1 = cc >> 1;
+        const int nc = TX / 2 + e;
+        const int r = local / nc, col = local - (local / nc) * nc;
+        const int xa = x0 - e, ya = y0 - e;
+        ic[m] = c;
+        plo[m] = max(1, z0 - e);
+        phi[m] = min(n - 1, z1 - 1 + e);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            // P = s - 2c has the parity sp of the step
+            const int i = xa + ((xa + c1 + sp) & 1) + 2 * col;
+            const int j = ya + ((ya + c1 + sp + c0) & 1) + 2 * r;
+            const int lx = i - lx0;
+            lio[m][sp] = (j - ly0) * LX + (lx & 1) * HW + (lx >> 1);
+            gio[m][sp] = i + sy * j;
+            okxy[m][sp] = c >= 0 && i >= max(1, xa) && i <= min(n - 1, x1 - 1 + e) &&
+                          j >= max(1, ya) && j <= min(n - 1, y1 - 1 + e);
+            own[m][sp] = i >= x0 && i < x1 && j >= y0 && j < y1;
+        }
+    }
+    // item m has a node at step s (sp = s & 1, P = s - 2c)
+    auto active = [&](int m, int sp, int P) {
+        return okxy[m][sp] && P >= plo[m] && P <= phi[m];
+    };
+    auto fetch_f = [&](int s, double *f) {
+        const int sp = s & 1;
+#pragma unroll
+        for (int m = 0; m < MI; ++m) {
+            const int P = s - 2 * ic[m];
+            const bool ok = active(m, sp, P);
+            const double x = F[ok ? gio[m][sp] + sz * P : 0];
+            f[m] = x;
+        }
+    };
+
+    // ---- the update of item m at step s, right-hand side f.  The x
+    // parity of the node is uniform across the wavefront, so the branch on
+    // it is too, and each side reads its neighbours at constant offsets.
+    auto update = [&](int m, int s, double f) {
+        const int sp = s & 1;
+        const int c = ic[m];
+        const int P = s - 2 * c;
+        if (!active(m, sp, P))
+            return;
+        const int io = lio[m][sp];
+        double *C = su + slot(P) + io;
+        const double *D = su + slot(P - 1) + io;
+        const double *U = su + slot(P + 1) + io;
+        auto apply = [&](auto parity) {
+            constexpr int odd = decltype(parity)::value;
+            constexpr int xp = odd ? 1 - HW : HW;
+            constexpr int xm = odd ? -HW : HW - 1;
+            if (OP == OP_MA) {
+                const Hess h = hessian3(D, C, U, xp, xm, LX, G.s, G.s4);
+                bool nc = false;
+                C[0] = ma_point_update(h, C[0], f, G.hk, nc);
+                // recomputed halo nodes are counted by their own column / chunk
+                if (nc && ncount && own[m][sp] && P >= z0 && P < z1)
+                    atomicAdd(ncount + G.slot, 1ull);
+            } else {
+                const double lap = laplacian3(D, C, U, xp, xm, LX, G.s);
+                C[0] = lap_point_update(lap, C[0], f, G.hk);
+            }
+        };
+        if (((c >> 1) + sp - lx0) & 1)
+            apply(std::integral_constant<int, 1>{});
+        else
+            apply(std::integral_constant<int, 0>{});
+    };
+
+    // ---- write plane q (owned nodes and the Dirichlet layer beside them)
+    const int xs0 = x0 == 1 ? 0 : x0, xs1 = x1 == n ? n + 1 : x1;
+    const int ys0 = y0 == 1 ? 0 : y0, ys1 = y1 == n ? n + 1 : y1;
+    auto store_plane = [&](int q) {
+        const double *b = su + slot(q);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int el = tid + k * NT;
+            const int bb = el / SX, a = el - (el / SX) * SX;
+            const int gx = xs0 + a, gy = ys0 + bb;
+            if (el < SX * SY && gx < xs1 && gy < ys1) {
+                const int lx = gx - lx0;
+                uout[gx + sy * gy + sz * q] = b[(gy - ly0) * LX + (lx & 1) * HW + (lx >> 1)];
+            }
+        }
+    };
+
+    // ---- the walk.  Steps S0..S1 update; plane q is stored at step q + 7.
+    // Loads run three steps ahead: the plane written to LDS at the end of
+    // step s (s + 2) and the right-hand sides used at step s were issued at
+    // step s - 2, so each step's loads have two steps to arrive.
+    const int S0 = max(1, z0 - 3);
+    const int S1 = min(n - 1, z1 - 1) + 6;
+    {
+        double v[KL];
+        for (int p = S0 - 1; p <= S0 + 1; ++p) {
+            fetch_plane(p, v);
+            put_plane(p, v);
+        }
+    }
+    double p0[KL], p1[KL], p2[KL];   // plane prefetch buffers (rotate by step)
+    double f0[MI], f1[MI], f2[MI];   // right-hand sides of the next steps' items
+    fetch_plane(S0 + 2, p1);
+    fetch_plane(S0 + 3, p2);
+    fetch_f(S0, f0);
+    fetch_f(S0 + 1, f1);
+    lds_barrier();
+    // the Dirichlet planes travel with the chunk next to them
+    if (z0 == 1)
+        store_plane(0);
+
+    // one step: issue the loads of plane s+4 into pn and of the right-hand
+    // sides of step s+2 into fn, store plane s-7, update with fc, then write
+    // plane s+2 (loaded two steps earlier into pw) to LDS
+    auto step = [&](int s, double *pn, double *pw, double *fc, double *fn) {
+        fetch_plane(s + 4, pn);
+        fetch_f(s + 2, fn);
+        const int q = s - 7;
+        if (q >= z0 && q < z1) {
+            store_plane(q);
+            if (q == n - 1)
+                store_plane(n);
+        }
+        if (s <= S1) {
+#pragma unroll
+            for (int m = 0; m < MI; ++m)
+                update(m, s, fc[m]);
+        }
+        put_plane(s + 2, pw);
+        lds_barrier();
+    };
+    for (int s = S0; s <= S1 + 1; s += 3) {
+        step(s, p0, p1, f0, f2);
+        if (s + 1 > S1 + 1)
+            break;
+        step(s + 1, p1, p2, f1, f0);
+        if (s + 2 > S1 + 1)
+            break;
+        step(s + 2, p2, p0, f2, f1);
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; tile_of_block gives
+// each XCD a contiguous range of columns (x fastest, then y, then the z
+// chunk), so columns that share halos share an L2.
+template <int OP, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_zsweep(const FsList *__restrict__ L,
+                                               unsigned long long *__restrict__ ncount)
+{
+    __shared__ double su[ZsShape<TX, TY>::NL];
+    const int total = L->total;
+    const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
+    if (t >= total)
+        return;
+    const int ng = L->ngrids;
+    int g = 0;
+    while (g + 1 < ng && L->g[g + 1].start <= t)
+        ++g;
+    const FsGrid G = L->g[g];
+    if ((L->stopped >> G.slot) & 1ull)
+        return;
+    zsweep_tile<OP, TX, TY, NT>(G, t - G.start, su, ncount);
+}
+
+template <int OP, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_zsweep1(FsGrid G, unsigned long long *__restrict__ ncount)
+{
+    __shared__ double su[ZsShape<TX, TY>::NL];
+    const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
+    zsweep_tile<OP, TX, TY, NT>(G, t, su, ncount);
+}
+
+} // namespace mafas

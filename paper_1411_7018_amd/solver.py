@@ -74,15 +74,20 @@ class Solver:
         L.ma_set_stream(self.handle, _stream_handle(stream))
 
     def retune(self, coarse_n: int | None = None, max_blocks: int | None = None,
-               strip_rows: int | None = None, block_n: int | None = None) -> None:
+               strip_rows: int | None = None, block_n: int | None = None,
+               zsweep_n: int | None = None, tile_config: int | None = None) -> None:
         """Change the launch shape of later cycles (results are unchanged)."""
         cn = self.params.coarse_n if coarse_n is None else int(coarse_n)
         mb = self.params.max_blocks if max_blocks is None else int(max_blocks)
         sr = self.params.strip_rows if strip_rows is None else int(strip_rows)
         bn = self.params.block_n if block_n is None else int(block_n)
+        zn = self.params.zsweep_n if zsweep_n is None else int(zsweep_n)
+        tc = self.params.tile_config if tile_config is None else int(tile_config)
         L.ma_retune(self.handle, cn, mb, sr, bn)
+        L.ma_retune_smoother(self.handle, bn, zn, tc)
         p = self.params
         p.coarse_n, p.max_blocks, p.strip_rows, p.block_n = cn, mb, sr, bn
+        p.zsweep_n, p.tile_config = zn, tc
 
     def _grid(self, t: torch.Tensor, n: int | None = None, name: str = "u") -> int:
         n = self.n if n is None else n

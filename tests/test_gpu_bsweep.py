@@ -46,9 +46,10 @@ def start(p, seed):
     return P.initial_guess(p, p.u_exact * (1.0 + 1e-3 * rng.standard_normal(p.u_exact.shape)))
 
 
-# ragged grids (n - 1 not a multiple of the block sides) and tiny ones
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6, 7])
-@pytest.mark.parametrize("n", [4, 9, 33, 47, 64, 100])
+# ragged grids (n - 1 not a multiple of the block sides) and tiny ones;
+# configurations 8..11 are the z-stream sweeps
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("n", [2, 4, 9, 33, 47, 64, 100])
 def test_block_sweep_bitwise_vs_color_and_oracle(n, cfg):
     note("block sweep", n, cfg)
     p = P.exp_cos(n, seed=n + cfg)
