@@ -1,23 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the FAS multigrid Monge-Ampere solver on one MI355X.
 
-Default workload (one step = one complete solve): the 129^3 seeded quadratic
-problem (u = x^T A x / 2 + b^T x, A SPD with eigenvalues in [0.5, 2],
-f = det A): Poisson initial guess, then FAS V(2,2) cycles until the relative
-discrete L2 residual is <= 1e-8, every input resident in HBM before timing
-starts.  Other workloads:
-  example4_17, expcos257, expcos385   single solves of other sizes;
+Default workload: the served stream -- Poisson arrivals of solve requests
+with grid sizes 65^3 / 129^3 / 257^3 / 385^3 (p = .4/.3/.2/.1), quadratic or
+exp-cos data, relative discrete L2 residual 1e-8, through the
+continuous-batching server (HBM-budgeted admission, resident hierarchies, one
+resident batch per size class).  One step is 16 requests of the arrival
+trace; the arrival rate is 0.8 x the measured capacity of the same mix
+solved one request at a time.  The request data are on the device before
+the clock starts.  The same trace is served in the plain FP64 form (the
+value), in the mixed FP32/FP64 form and with a 4 GiB budget that forces
+admission queueing.  Other workloads:
+  quadratic129, example4_17, expcos257, expcos385   single solves (one step =
+            one solve, Poisson initial guess, FAS V(2,2) to 1e-8);
   batch64   64 seeded solves (sizes 33^3..129^3, quadratic or exp-cos) run
             as one batch; one step = the whole batch;
-  served    a Poisson-arrival stream of requests (65^3..385^3) through the
-            continuous-batching server; --steps requests.
-Before timing, the autotuner picks the engine's launch shapes on the same
-solvers and data (outside the timed region; --no-tune keeps the defaults).
+  *_fmg, gs_*, ex2d*  the Section 4 protocol, the standalone Gauss-Seidel
+            solver and the 2D variant.
+Before timing a single solve or the batch, the autotuner picks the engine's
+launch shapes on the same solvers and data (outside the timed region;
+--no-tune keeps the defaults).
 
 Prints one JSON line: solves/s (value), p50/p99 latency, grid-point
 updates/s, the finest-level smoother's algorithmic bandwidth against the HBM
-peak (HIP events around its launches inside the timed region), and, for the
-default run, the CPU oracle timed on a bounded sample of the same workload.
+peak (HIP events on the engine stream around its launches, in an
+instrumented pass), and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -35,10 +43,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Counter-measured bytes per launch of the dominant kernel (FETCH_SIZE and
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
-# known size): profiles/k_batched_sweep_quadratic129_counters.md.  Valid for
-# the k_batched sweep kernel as profiled; reset to None when it changes.
-SERVE_RATE = 30.0   # served stream: Poisson arrivals per second
-TRAFFIC = {("quadratic129", "fp64"): 31601357}
+# known size), keyed by (workload, kernel); valid only for the kernel as it
+# was profiled.
+TRAFFIC = {}
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
@@ -64,9 +71,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (served: requests); default per workload")
+                    help="timed steps (served: blocks of 16 requests); default per workload")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="quadratic129", choices=WORKLOADS)
+    ap.add_argument("--workload", default="served", choices=WORKLOADS)
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64, except batch64 (mixed)")
     ap.add_argument("--init", default=None, choices=["poisson", "fmg"],
@@ -81,7 +88,8 @@ def parse():
                          "calibration for the traffic figures) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=None,
-                    help=f"served: arrivals per second (default {SERVE_RATE:g})")
+                    help="served: arrivals per second (default 0.8 x the measured "
+                         "one-at-a-time capacity of the size mix)")
     ap.add_argument("--budget-gb", type=float, default=None, help="served: HBM budget")
     ap.add_argument("--lanes", default="65/129/257/385",
                     help="served: size classes in points per side, '/' between classes and "
@@ -412,49 +420,232 @@ def run_batch(args, precision):
     return out
 
 
-def run_served(args, precision):
+STEP_REQUESTS = 16       # served stream: requests of the arrival trace per bench step
+SMALL_BUDGET_GB = 4.0    # served stream: the budget that forces admission queueing
+
+
+def solo_capacity(precision):
+    """Solves/s of the served size mix when every request is solved alone,
+    one after the other: 1 / sum_n w_n t_n with t_n the solo solve time of an
+    n grid (mean of a quadratic and an exp-cos problem, graphs warm)."""
+    import torch
+
+    from paper_1411_7018_amd import Solver, problems as P
+
+    times = {}
+    for n in P.SERVE_SIZES:
+        ts = []
+        s = Solver(n, precision=precision)
+        for kind, seed in (("quadratic", 91), ("exp_cos", 92)):
+            u0, f = P.make_device(kind, n, seed)
+            u = u0.clone()
+            s.solve(u, f, tol=1e-8)
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.solve(u, f, tol=1e-8)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            del u0, f, u
+        s.close()
+        times[n] = sum(ts) / len(ts)
+    mean = sum(w * times[n] for n, w in zip(P.SERVE_SIZES, P.SERVE_WEIGHTS))
+    return 1.0 / mean, times
+
+
+def serve(server, trace, keep=None):
+    """Serve one arrival trace whose request data are already on the device
+    (the client's payloads, made before the clock starts)."""
     import torch
 
     from paper_1411_7018_amd import problems as P
-    from paper_1411_7018_amd.server import GpuBackend, Server, requests_from_trace
+    from paper_1411_7018_amd.server import requests_from_trace
 
-    count = args.steps or 256
-    warmup = 8 if args.warmup is None else args.warmup
-    # a fixed arrival rate, below what one GPU serves of this size mix (about
-    # 38 solves/s in FP64): the latencies then measure service and ordinary
-    # queueing, not a queue that grows without bound
-    rate = SERVE_RATE if args.rate is None else args.rate
-    budget = int(args.budget_gb * (1 << 30)) if args.budget_gb else GpuBackend.budget_default()
+    reqs = requests_from_trace(trace)
+    for r in reqs:
+        r.payload = P.make_device(r.kind, r.n, r.seed)
+    torch.cuda.synchronize()
+    server.keep_results = keep is not None
+    st = server.run(reqs)
+    torch.cuda.synchronize()
+    if keep is not None:
+        for r in reqs:
+            if r.rid not in keep:
+                r.u = None
+    return st, reqs
+
+
+def served_cpu_baseline(cycles_by_n):
+    """The oracle (serial C, one core) on a bounded sample of the served
+    mix: one linear and one FAS V-cycle (and a residual) timed at 65^3,
+    129^3 and 257^3, the 385^3 times extrapolated from 257^3 by the ratio of
+    interior nodes; combined with the cycle counts the served solves took
+    into seconds per request, and requests/s for the size mix."""
+    import platform
+
+    import torch
+
+    import oracle
+    from paper_1411_7018_amd import problems as P
+
+    per, unit = {}, {}
+    spent = 0.0
+    timed = [n for n in P.SERVE_SIZES if n <= 256]
+    for n in timed:
+        u0, f = P.make_device("exp_cos", n, 777)
+        u, fh = u0.cpu().numpy(), f.cpu().numpy()
+        del u0, f
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        oracle.poisson_vcycle(u, oracle.poisson_rhs(fh))
+        t_lin = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.vcycle(u, fh)
+        t_fas = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.residual(u, fh, out=False)
+        t_res = time.perf_counter() - t0
+        spent += t_lin + t_fas + t_res
+        unit[n] = (t_lin, t_fas, t_res)
+    for n in P.SERVE_SIZES:
+        if n not in unit:
+            ref = max(timed)
+            k = ((n - 1) / (ref - 1)) ** 3
+            unit[n] = tuple(k * t for t in unit[ref])
+        t_lin, t_fas, t_res = unit[n]
+        init_c, main_c = cycles_by_n.get(n, (6.0, 12.0))
+        per[n] = init_c * (t_lin + t_res) + main_c * (t_fas + t_res)
+    mean = sum(w * per[n] for n, w in zip(P.SERVE_SIZES, P.SERVE_WEIGHTS))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor() or "unknown"
+    return {"value": 1.0 / mean, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_nproc": os.cpu_count(),
+            "seconds_per_request": {str(n + 1): per[n] for n in P.SERVE_SIZES},
+            "sample": f"one linear and one FAS V(2,2) cycle plus a residual of an exp-cos "
+                      f"problem at 65^3, 129^3 and 257^3 ({spent:.1f} s in all; 385^3 "
+                      f"extrapolated from 257^3 by the ratio of interior nodes), scaled by "
+                      f"the mean cycle counts of the served solves of each size and averaged "
+                      f"over the size mix (.4/.3/.2/.1)"}
+
+
+def served_roofline():
+    """Instrumented solves of a 385^3 request (the largest share of the
+    served GPU time) with the served launch shape: HIP events on the engine
+    stream around the finest-level smoother launches."""
+    import torch
+
+    from paper_1411_7018_amd import Solver, problems as P
+
+    n = 384
+    u0, f = P.make_device("exp_cos", n, 5001)
+    sp = Solver(n, profile=1)
+    u = u0.clone()
+    sp.solve(u, f, tol=1e-8)
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(2):
+        u.copy_(u0)
+        reps.append(sp.solve(u, f, tol=1e-8))
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    r = roofline(reps, TRAFFIC.get(("served", "k_zsweep")))
+    r["kernel"] = ("finest-level smoother of a 385^3 request: z-stream sweeps (k_zsweep, all "
+                   "four colour phases per launch; Monge-Ampere and Poisson sweeps), 24 B per "
+                   "interior node per sweep")
+    r.update(instrumented(reps, tp, 1))
+    r["pass"] = ("two instrumented 385^3 exp-cos solves after the served runs, HIP events on "
+                 "the engine stream around every group of finest-level sweep launches")
+    sp.close()
+    return r
+
+
+def run_served(args, precision):
+    import numpy as np
+    import torch
+
+    from paper_1411_7018_amd import problems as P
+    from paper_1411_7018_amd.server import GpuBackend, Server
+
+    steps = args.steps or 16
+    warmup = 2 if args.warmup is None else args.warmup
+    count = steps * STEP_REQUESTS
     lanes = None
     if args.lanes and args.lanes != "none":
         # classes of grid sizes in points per side (65, 129, ...); requests carry n
         lanes = [[int(p) - 1 for p in c.split(",")] for c in args.lanes.split("/")]
-    be = GpuBackend(precision=precision, tol=1e-8, max_slots=64)
-    if warmup:
-        Server(be, budget, lanes=lanes).run(
-            requests_from_trace(P.arrival_trace(warmup, rate, seed=4999)))
-    torch.cuda.synchronize()
-    reqs = requests_from_trace(P.arrival_trace(count, rate, seed=5000))
-    srv = Server(be, budget, max_slots=64, lanes=lanes)
-    t0 = time.perf_counter()
-    st = srv.run(reqs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    lat = [r.latency for r in reqs if r.status == 0]
-    out = base_line(args, st.solves_per_s, count, warmup, elapsed, lat, precision)
+    cap, solo = solo_capacity("fp64")
+    rate = args.rate if args.rate is not None else 0.8 * cap
+    trace = P.arrival_trace(count, rate, seed=5000)
+    warm = P.arrival_trace(max(warmup * STEP_REQUESTS, 1), rate, seed=4999) if warmup else None
+    budget = (int(args.budget_gb * (1 << 30)) if args.budget_gb
+              else GpuBackend.budget_default())
+    sample = set(range(0, count, 8))
+
+    def form(prec, bud, keep=None):
+        srv = Server(GpuBackend(precision=prec, tol=1e-8, max_slots=64), bud, max_slots=64,
+                     lanes=lanes)
+        if warm:
+            serve(srv, warm)
+        st, reqs = serve(srv, trace, keep)
+        lat = [r.latency for r in reqs if r.status == 0]
+        rec = {"solves_per_s": st.solves_per_s, "p50_ms": 1e3 * st.p50,
+               "p99_ms": 1e3 * st.p99, "completed": st.completed, "rejected": st.rejected,
+               "makespan_s": st.makespan, "queued": st.queued, "max_live": st.max_live,
+               "peak_bytes": st.peak_bytes, "budget_bytes": bud,
+               # requests that ended without meeting the tolerance: their
+               # start was so close that tol x r0 lies under the FP64 floor,
+               # where the residual stalls (status 4 after a few cycles)
+               "not_converged": [{"n": r.n, "kind": r.kind, "seed": r.seed,
+                                  "rel_res": r.report["rel_res"] if r.report else None,
+                                  "cycles": r.report["cycles"] if r.report else None}
+                                 for r in reqs if r.status not in (0, None) and r.status != 2]}
+        reports = [(r.n, r.report) for r in reqs if r.status == 0 and r.report]
+        return rec, reqs, lat, reports
+
+    plain, preqs, plat, plain_reports = form("fp64", budget, sample)
+    mixed, mreqs, _, _ = form("mixed", budget, sample)
+    diffs = [float((m.u - p.u).abs().max()) for p, m in zip(preqs, mreqs)
+             if p.u is not None and m.u is not None]
+    mixed["max_abs_diff_vs_fp64"] = max(diffs) if diffs else None
+    mixed["diff_sample"] = f"{len(diffs)} requests (every 8th), max-norm against the FP64 result"
+    del preqs, mreqs
+    small, sreqs, _, _ = form("fp64", int(SMALL_BUDGET_GB * (1 << 30)))
+    del sreqs
+    torch.cuda.empty_cache()
+    out = base_line(args, plain["solves_per_s"], steps, warmup, plain["makespan_s"], plat,
+                    "fp64")
     out["config"] = {
-        "workload": f"served stream: {count} Poisson arrivals at {rate:.1f}/s, sizes "
+        "workload": f"served stream: {count} Poisson arrivals at {rate:.1f}/s (0.8 x the "
+                    f"measured one-at-a-time capacity of {cap:.1f} solves/s unless set), sizes "
                     f"65^3/129^3/257^3/385^3 (p=.4/.3/.2/.1), quadratic or exp-cos, tol 1e-8, "
-                    f"{precision}, HBM budget {budget / 2**30:.1f} GiB, continuous batching, "
+                    f"fp64, HBM budget {budget / 2**30:.1f} GiB, continuous batching, "
                     + (f"lanes {args.lanes}" if lanes else "one resident batch"),
-        "requests": count, "rate_per_s": rate, "budget_bytes": budget, "precision": precision,
-        "lanes": args.lanes if lanes else None,
-        "latency": "completion - arrival"}
-    out.update({"completed": st.completed, "rejected": st.rejected,
-                "mean_live": st.mean_live, "max_live": st.max_live, "queued": st.queued,
-                "peak_bytes": st.peak_bytes, "ticks": st.ticks,
-                "updates_per_s": sum(r.report["point_updates"] for r in reqs if r.report)
-                / st.makespan})
+        "requests": count, "rate_per_s": rate, "capacity_one_at_a_time_per_s": cap,
+        "solo_ms": {str(n + 1): 1e3 * t for n, t in solo.items()},
+        "budget_bytes": budget, "precision": "fp64", "lanes": args.lanes if lanes else None,
+        "step": f"{STEP_REQUESTS} requests of the arrival trace",
+        "latency": "completion - arrival",
+        "request_data": "on the device before the clock starts (the client's payload)"}
+    by_n = {}
+    for n, rep in plain_reports:
+        by_n.setdefault(n, []).append(rep)
+    cyc = {n: (float(np.mean([r["init_cycles"] for r in reps])),
+               float(np.mean([r["cycles"] for r in reps]))) for n, reps in by_n.items()}
+    out.update({"forms": {"fp64": plain, "mixed": mixed}, "small_budget": small,
+                "chosen_form": "fp64",
+                "updates_per_s": sum(r["point_updates"] for _, r in plain_reports)
+                / plain["makespan_s"],
+                "cycles_by_size": {str(n + 1): list(c) for n, c in cyc.items()},
+                "roofline": served_roofline()})
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = served_cpu_baseline(cyc)
     return out
 
 

@@ -37,7 +37,8 @@ typedef enum {
     MA_ERR_ARG = 1,            /* invalid argument (sizes, null pointers)      */
     MA_ERR_OOM = 2,            /* device allocation failed                     */
     MA_ERR_DEVICE = 3,         /* a HIP call or kernel launch failed           */
-    MA_ERR_NOT_CONVERGED = 4,  /* max_cycles spent; the report is still filled */
+    MA_ERR_NOT_CONVERGED = 4,  /* max_cycles spent, or the residual stagnated
+                                  above the tolerance; the report is filled    */
     MA_ERR_NONFINITE = 5       /* a residual norm became NaN or Inf            */
 } ma_status;
 
@@ -188,8 +189,11 @@ ma_status ma_retune_smoother(ma_solver *s, int block_n, int zsweep_n, int tile_c
  * the initial guess.  u: device (n+1)^3, Dirichlet layer = g, interior = the
  * initial guess on entry (or replaced when flags has MA_INIT_POISSON) and
  * the solution on exit.  f: device (n+1)^3, interior read.  rep may be NULL.
- * Returns MA_ERR_NOT_CONVERGED when max_cycles run out (u holds the last
- * iterate), MA_ERR_NONFINITE when a norm is not finite. */
+ * Returns MA_ERR_NOT_CONVERGED when max_cycles run out, or when the residual
+ * has failed to drop below 0.9 x its best value for three cycles in a row
+ * while above the tolerance (it sits on the round-off floor: a start so
+ * close to the solution that tol * res0 lies under the floor); u holds the
+ * last iterate.  MA_ERR_NONFINITE when a norm is not finite. */
 ma_status ma_solve(ma_solver *s, double *u, const double *f, double tol, unsigned flags,
                    ma_report *rep);
 

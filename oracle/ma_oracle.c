@@ -714,10 +714,13 @@ long mao_fmg(int n, double *u, const double *f, const mao_params *p)
 
 /* Full solve (Algorithm 1 repeated under the Section 4 stopping rule).
  * hist (optional, hist_cap entries) receives the discrete L2 residual after
- * each cycle.  Limit mode (tol < 0): cycle until the residual has failed to
- * drop below 0.9 x its best value for three cycles in a row, i.e. until it
- * sits on the round-off floor.  Returns 0 when converged, 1 when max_cycles
- * ran out, -1 on allocation failure. */
+ * each cycle.  The residual stalls when it fails to drop below 0.9 x its
+ * best value for three cycles in a row, i.e. it sits on the round-off floor.
+ * Limit mode (tol < 0): cycle until it stalls.  With a tolerance: cycle
+ * until the relative residual is <= tol, or until it stalls above it (a start
+ * so close to the solution that tol x r0 lies under the floor: not
+ * converged), or max_cycles.  Returns 0 when converged, 1 when not, -1 on
+ * allocation failure. */
 int mao_solve(int n, double *u, const double *f, const mao_params *p, mao_report *rep,
               double *hist, int hist_cap)
 {
@@ -770,19 +773,24 @@ int mao_solve(int n, double *u, const double *f, const mao_params *p, mao_report
             rep->res = l2_from_sumsq(n, residual_op(n, u, f, NULL, 0));
             if (hist && c < hist_cap)
                 hist[c] = rep->res;
+            /* the residual's best value so far and the cycles since it last
+             * dropped below 0.9 x that best */
+            const int stalled = rep->res < 0.9 * best ? 0 : stall + 1;
+            if (stalled == 0)
+                best = rep->res;
+            stall = stalled;
             if (p->tol >= 0.0) {
                 if (rep->res <= p->tol * rep->res0) {
                     status = 0;
                     break;
                 }
-            } else {
-                if (rep->res < 0.9 * best) {
-                    best = rep->res;
-                    stall = 0;
-                } else if (++stall >= 3) {
-                    status = 0;
+                /* stagnation above the tolerance: three cycles in a row on
+                 * the round-off floor cannot reach it; not converged */
+                if (stall >= 3)
                     break;
-                }
+            } else if (stall >= 3) {
+                status = 0;
+                break;
             }
         }
     }

@@ -128,6 +128,10 @@ struct SolveState {
     // the phase's last two norms read (prev 0: only the phase's start is
     // known), for the guess whether the tick being read will stop the solve
     double last = 0.0, prev = 0.0;
+    // the main phase's best residual so far and the cycles since it last
+    // dropped below 0.9 x that best (three in a row: stagnation)
+    double best = 0.0;
+    int stall = 0;
 };
 
 // The FMG start of a solve (Section 4 protocol): zero the interior of u, take

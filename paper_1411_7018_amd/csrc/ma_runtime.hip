@@ -828,6 +828,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                     r.res = r.history[0] = nrm[i];
                     st->last = nrm[i];
                     st->prev = 0.0;
+                    st->best = r.res0;
+                    st->stall = 0;
                     r.rel_res = r.res0 > 0.0 ? r.res / r.res0 : 0.0;
                     if (!std::isfinite(nrm[i]))
                         finish(st, MA_ERR_NONFINITE, "residual after FMG is not finite");
@@ -843,6 +845,8 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 }
                 st->rep.res0 = st->rep.res = st->last = nrm[i];
                 st->prev = 0.0;
+                st->best = nrm[i];
+                st->stall = 0;
                 if (!std::isfinite(nrm[i]))
                     finish(st, MA_ERR_NONFINITE, "initial residual is not finite");
                 else if (nrm[i] == 0.0) {
@@ -866,7 +870,10 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 const double c = states[i]->tol * r.res0;
                 thr[i] = sum_threshold(c, p.n);
                 const int done = main_mode == Engine::MODE_MIXED ? r.outer : r.cycles;
-                spec &= done + 2 <= p.max_cycles && goes_on(states[i], c);
+                // a stall stop is the host's own decision too: no tick ahead
+                // of one that could make it
+                spec &= done + 2 <= p.max_cycles && goes_on(states[i], c) &&
+                        states[i]->stall + 1 < 3;
             }
         MA_TRY(eng.tick_ahead(main_mode, act, thr, spec, nrm));
         for (int i = 0; i < S; ++i)
@@ -896,11 +903,18 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 st->prev = st->last;
                 st->last = nrm[i];
                 r.rel_res = r.res / r.res0;
+                const int stalled = r.res < 0.9 * st->best ? 0 : st->stall + 1;
+                if (stalled == 0)
+                    st->best = r.res;
+                st->stall = stalled;
                 if (!std::isfinite(r.res)) {
                     finish(st, MA_ERR_NONFINITE, "residual is not finite");
                 } else if (r.res <= st->tol * r.res0) {
                     r.converged = 1;
                     finish(st, MA_OK, "");
+                } else if (st->stall >= 3) {
+                    finish(st, MA_ERR_NOT_CONVERGED,
+                           "the residual stagnated above the tolerance (round-off floor)");
                 } else if (steps >= p.max_cycles) {
                     finish(st, MA_ERR_NOT_CONVERGED, "max_cycles reached before the tolerance");
                 }

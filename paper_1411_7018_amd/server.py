@@ -69,6 +69,7 @@ class Request:
     status: int | None = None   # 0 converged, else an ma_status
     report: dict | None = None
     u: object = None            # the solution (kept when keep_results)
+    payload: object = None      # (u0, f) already on the device, or None: made on admission
 
     @property
     def latency(self) -> float:
@@ -103,6 +104,12 @@ class GpuBackend:
         return Solver(n, precision=self.precision, **self.params)
 
     def data(self, req: Request):
+        """The request's (u, f): its payload when the client has put it on
+        the device already, else made now on the current stream."""
+        if req.payload is not None:
+            u, f = req.payload
+            req.payload = None
+            return u, f
         from .problems import make_device
 
         return make_device(req.kind, req.n, req.seed)

@@ -261,3 +261,25 @@ def test_nonpositive_f_counted_as_nonconvex():
     nc = s.sweep(u, dev(f), 1)
     assert nc == nc_o == 8
     assert relmax(host(u), want) <= TOL
+
+
+def test_stagnation_above_tolerance_stops_early_like_oracle():
+    """Start within round-off of a quadratic's solution, tolerance under the
+    FP64 floor: the GPU solve stops not converged once the residual stalls,
+    as the oracle does, with a solution at round-off."""
+    from paper_1411_7018_amd import Solver, _lib as L
+    n = 32
+    p = P.quadratic(n, seed=77)
+    x, y, z = P.grid(n)
+    u0 = p.u_exact + 1e-9 * np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+    want = u0.copy()
+    ost, orep, _ = oracle.solve(want, p.f, oracle.params(tol=1e-12, max_cycles=60, init=False))
+    assert ost == 1
+    u = torch.from_numpy(u0).cuda()
+    with pytest.raises(L.MAError) as ei:
+        Solver(n, max_cycles=60).solve(u, torch.from_numpy(p.f).cuda(), tol=1e-12, init="none")
+    assert ei.value.status == L.MA_ERR_NOT_CONVERGED
+    rep = ei.value.report
+    assert 4 <= rep["cycles"] <= 15 and rep["converged"] == 0
+    torch.cuda.synchronize()
+    assert np.abs(u.cpu().numpy() - p.u_exact).max() <= 1e-13 * np.abs(p.u_exact).max()

@@ -256,3 +256,20 @@ def test_limit_mode_reaches_roundoff_floor():
     st, rep, hist = oracle.solve_limit(u, p.f)
     assert st == 0
     assert rep.res / rep.res0 < 1e-12
+
+
+def test_stagnation_above_tolerance_stops_early():
+    """A start within round-off of a quadratic's exact discrete solution: the
+    relative tolerance lies under the FP64 floor, the residual stalls (three
+    cycles in a row without dropping below 0.9 x its best) and the solve
+    stops not converged, long before max_cycles."""
+    p = P.quadratic(32, seed=77)
+    x, y, z = P.grid(32)
+    bump = np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+    u = p.u_exact + 1e-9 * bump
+    st, rep, hist = oracle.solve(u, p.f, oracle.params(tol=1e-12, max_cycles=60, init=False))
+    assert st == 1 and rep.converged == 0
+    assert 4 <= rep.cycles <= 15
+    assert rep.res > 1e-12 * rep.res0
+    # it did reach the floor: the solution is the quadratic to round-off
+    assert np.abs(u - p.u_exact).max() <= 1e-13 * np.abs(p.u_exact).max()
