@@ -208,6 +208,23 @@ ma_status ma_vcycle(ma_solver *s, double *u, const double *f);
 ma_status ma_residual(ma_solver *s, const double *u, const double *f, double *r_or_null,
                       double *l2_host);
 
+/* For callers that cannot allocate device memory -- code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * residual and norm of ma_residual with no solver and no allocation.
+ * n (2 <= n <= MA_NOALLOC_MAX_N): intervals per side; u, f: device
+ * (n+1)^3 FP64, x fastest; r_or_null: device (n+1)^3 or NULL, receives
+ * r = f - det(D^2_h u) inside and 0 on the boundary; l2_dev: one device
+ * double, receives sqrt(h^3 sum r^2).  Everything is enqueued on hip_stream
+ * (NULL: the null stream) and nothing is waited for.  The norm partials live
+ * in a fixed device array of 4 MiB that the library holds on every device it
+ * runs on until the process ends; all calls on one device share it, so calls
+ * that overlap on one device race.  Errors: MA_ERR_ARG for n outside
+ * 2..MA_NOALLOC_MAX_N or null u, f, l2_dev (message in ma_last_error(NULL)),
+ * MA_ERR_DEVICE when a launch fails. */
+#define MA_NOALLOC_MAX_N 512
+ma_status ma_residual_noalloc(int n, const double *u, const double *f, double *r_or_null,
+                              double *l2_dev, void *hip_stream);
+
 /* count nonlinear Gauss-Seidel sweeps (Section 2, eqs. 2.8-2.9: each point
  * takes the smallest real root of its local cubic) on the finest grid, in
  * the solver's colour ordering.  u in place, f read.  nonconvex_host (may be

@@ -93,6 +93,8 @@ _L.ma_last_error.restype = ctypes.c_char_p
 _L.ma_set_stream.argtypes = [_vp, _vp]
 _L.ma_retune.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
 _L.ma_retune_smoother.argtypes = [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_L.ma_residual_noalloc.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
+_L.ma_residual_noalloc.restype = ctypes.c_int
 _L.ma_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_uint, _R]
 _L.ma_vcycle.argtypes = [_vp, _vp, _vp]
 _L.ma_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
@@ -143,7 +145,8 @@ for _name in ("ma_create", "ma_set_stream", "ma_retune", "ma_retune_smoother", "
 EXPORTS = ("ma_params_default", "ma_footprint_bytes", "ma_levels", "ma_create", "ma_destroy",
            "ma_last_error", "ma_set_stream", "ma_retune", "ma_retune_smoother", "ma_solve",
            "ma_vcycle",
-           "ma_residual", "ma_sweep", "ma_restrict", "ma_prolong_correct", "ma_poisson_init",
+           "ma_residual", "ma_residual_noalloc", "ma_sweep", "ma_restrict",
+           "ma_prolong_correct", "ma_poisson_init",
            "ma_fmg", "ma_gs_solve", "ma_solve_batch", "ma_batch_create", "ma_batch_destroy",
            "ma_batch_last_error", "ma_batch_add", "ma_batch_tick", "ma_batch_report",
            "ma_batch_remove", "ma2d_params_default", "ma2d_footprint_bytes", "ma2d_create",
@@ -200,6 +203,14 @@ def ma_set_stream(h: int, stream: int | None) -> None:
 
 def ma_retune(h: int, coarse_n: int, max_blocks: int, strip_rows: int, block_n: int = 0) -> None:
     _check(_L.ma_retune(h, int(coarse_n), int(max_blocks), int(strip_rows), int(block_n)), h)
+
+
+def ma_residual_noalloc(n: int, u: int, f: int, r: int | None, l2_dev: int, stream) -> None:
+    """The allocation-free residual (device pointers as integers; the norm
+    lands in the device double at l2_dev)."""
+    st = _L.ma_residual_noalloc(int(n), u, f, r or None, l2_dev, stream or None)
+    if st != MA_OK:
+        raise MAError(st, ma_last_error(None))
 
 
 def ma_retune_smoother(h: int, block_n: int, zsweep_n: int, tile_config: int) -> None:

@@ -12,6 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmafas.so")
 SOURCES = ["ma_kernels.hip", "ma_bsweep.hip", "ma_engine.hip", "ma_runtime.hip", "ma_mixed.hip",
+           "ma_static.hip",
            "ma_batch.hip", "ma2d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

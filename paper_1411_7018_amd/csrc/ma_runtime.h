@@ -63,6 +63,9 @@ hipError_t launch_fill_u64(hipStream_t st, size_t count, unsigned long long v,
 
 double now_seconds();
 
+// Sets the message ma_last_error(NULL) returns (calls without a solver).
+void set_global_error(const std::string &why);
+
 } // namespace mafas
 
 struct ma_solver {

@@ -89,6 +89,9 @@ bool valid_params(const ma_params *p, std::string &why)
 
 } // namespace
 
+// the message ma_last_error(NULL) returns, for calls that have no solver
+void mafas::set_global_error(const std::string &why) { g_create_error = why; }
+
 double mafas::now_seconds()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
