@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size), keyed by (workload, kernel); valid only for the kernel as it
 # was profiled.
-TRAFFIC = {}
+TRAFFIC = {("served", "k_zsweep"): 1.897e9}   # profiles/k_zsweep_expcos385.md
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
@@ -87,6 +87,9 @@ def parse():
                     help="only run 20 plain device copies of MB megabytes (counter "
                          "calibration for the traffic figures) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only run the instrumented 385^3 solves behind the served line's "
+                         "roofline and print that record (for kernel traces and counters)")
     ap.add_argument("--rate", type=float, default=None,
                     help="served: arrivals per second (default 0.8 x the measured "
                          "one-at-a-time capacity of the size mix)")
@@ -657,6 +660,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.roofline_only:
+        print(json.dumps({"roofline": served_roofline()}), flush=True)
         return
     precision = args.precision or ("mixed" if args.workload == "batch64" else "fp64")
     if args.workload in SINGLE:
