@@ -195,7 +195,8 @@ def retune_like(solvers, choice):
     if choice is not None:
         for s in solvers:
             s.retune(coarse_n=choice.coarse_n, max_blocks=choice.max_blocks,
-                     strip_rows=choice.strip_rows, block_n=choice.block_n)
+                     strip_rows=choice.strip_rows, block_n=choice.block_n,
+                     tile_config=choice.tile_config, zsweep_n=choice.zsweep_n)
 
 
 def instrumented(reps, elapsed, per_step):
@@ -211,6 +212,7 @@ def tune_note(choice):
         return None
     return {"coarse_n": choice.coarse_n, "max_blocks": choice.max_blocks,
             "strip_rows": choice.strip_rows, "block_n": choice.block_n,
+            "tile_config": choice.tile_config, "zsweep_n": choice.zsweep_n,
             "ms_per_tick": 1e3 * choice.seconds_per_tick}
 
 
@@ -591,12 +593,12 @@ def run_served(args, precision):
               else GpuBackend.budget_default())
     sample = set(range(0, count, 8))
 
-    def form(prec, bud, keep=None):
+    def form(prec, bud, keep=None, arrivals=trace):
         srv = Server(GpuBackend(precision=prec, tol=1e-8, max_slots=64), bud, max_slots=64,
                      lanes=lanes)
         if warm:
             serve(srv, warm)
-        st, reqs = serve(srv, trace, keep)
+        st, reqs = serve(srv, arrivals, keep)
         lat = [r.latency for r in reqs if r.status == 0]
         rec = {"solves_per_s": st.solves_per_s, "p50_ms": 1e3 * st.p50,
                "p99_ms": 1e3 * st.p99, "completed": st.completed, "rejected": st.rejected,
@@ -621,6 +623,10 @@ def run_served(args, precision):
     del preqs, mreqs
     small, sreqs, _, _ = form("fp64", int(SMALL_BUDGET_GB * (1 << 30)))
     del sreqs
+    # the same requests all arriving at once: the server's capacity
+    burst = [(0.0, kind, n, seed) for _, kind, n, seed in trace]
+    sat, breqs, _, _ = form("fp64", budget, arrivals=burst)
+    del breqs
     torch.cuda.empty_cache()
     out = base_line(args, plain["solves_per_s"], steps, warmup, plain["makespan_s"], plat,
                     "fp64")
@@ -642,6 +648,10 @@ def run_served(args, precision):
     cyc = {n: (float(np.mean([r["init_cycles"] for r in reps])),
                float(np.mean([r["cycles"] for r in reps]))) for n, reps in by_n.items()}
     out.update({"forms": {"fp64": plain, "mixed": mixed}, "small_budget": small,
+                "saturation": {"solves_per_s": sat["solves_per_s"], "p50_ms": sat["p50_ms"],
+                               "p99_ms": sat["p99_ms"], "makespan_s": sat["makespan_s"],
+                               "arrivals": "the same requests, all at t = 0",
+                               "vs_one_at_a_time": sat["solves_per_s"] / cap},
                 "chosen_form": "fp64",
                 "updates_per_s": sum(r["point_updates"] for _, r in plain_reports)
                 / plain["makespan_s"],

@@ -14,6 +14,11 @@ cut into launches:
   * ``block_n``    -- levels with n <= block_n (above coarse_n) smooth with
     block sweeps (the four colour phases of a sweep in one launch) instead
     of one launch per colour phase; -1 turns them off.
+  * ``tile_config`` -- the block shape of those block sweeps (0: picked by
+    the level's size and block count; 1..7 fixed shapes).
+  * ``zsweep_n``   -- levels with n >= zsweep_n smooth with z-stream sweeps
+    (four colour phases per launch, each workgroup walking a column plane by
+    plane); 0 automatic, -1 never.
 
 ``tune`` times the candidates on the device, on the caller's own
 solvers and data (a copy of u), with one tick per candidate for graph
@@ -35,6 +40,8 @@ BLOCKS = (4096, 8192, 16384, 32768, 65536, 131072, 262144)
 COARSE = (0, 8, 16, 32)
 STRIPS = (8, 32, 128, 4096)
 BLOCK_N = (-1, 32, 64)
+TILES = (0, 1, 2, 5, 6)
+ZSWEEP = (0, -1)
 
 
 @dataclasses.dataclass
@@ -44,11 +51,15 @@ class Choice:
     strip_rows: int
     block_n: int
     seconds_per_tick: float
-    table: list  # [(coarse_n, max_blocks, strip_rows, block_n, seconds_per_tick), ...]
+    # [(coarse_n, max_blocks, strip_rows, block_n, tile_config, zsweep_n, seconds_per_tick)]
+    table: list
+    tile_config: int = 0
+    zsweep_n: int = 0
 
     def as_dict(self) -> dict:
         return {"coarse_n": self.coarse_n, "max_blocks": self.max_blocks,
                 "strip_rows": self.strip_rows, "block_n": self.block_n,
+                "tile_config": self.tile_config, "zsweep_n": self.zsweep_n,
                 "seconds_per_tick": self.seconds_per_tick,
                 "table": [list(r) for r in self.table]}
 
@@ -79,15 +90,16 @@ def _time_ticks(solvers, us, fs, ticks: int) -> float:
 
 
 def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE, strips=STRIPS,
-         block_ns=BLOCK_N, verbose: bool = False) -> Choice:
+         block_ns=BLOCK_N, tiles=TILES, zsweeps=ZSWEEP, verbose: bool = False) -> Choice:
     """Pick the launch shape of one batched tick of these solves and retune
     the solvers to it.  The knobs barely interact (coarse_n moves work
     between the coarse-level kernel and the row kernels; max_blocks and
-    strip_rows shape the row kernels; block_n moves mid-level sweeps to the
-    block kernel), so they are searched one after the other -- coarse_n x
-    max_blocks on the default strips, then strip_rows, then block_n --
-    instead of over the full product.  The solves must fit one batch (at
-    most 64, shared smoothing parameters)."""
+    strip_rows shape the row kernels; block_n and tile_config move and shape
+    the mid-level block sweeps; zsweep_n moves the largest levels to the
+    z-stream sweep), so they are searched one after the other -- coarse_n x
+    max_blocks on the default strips, then strip_rows, then block_n, then
+    tile_config, then zsweep_n -- instead of over the full product.  The
+    solves must fit one batch (at most 64, shared smoothing parameters)."""
     if not solvers:
         raise ValueError("nothing to tune")
     if any(s.params.max_cycles < ticks + 1 for s in solvers):
@@ -100,32 +112,42 @@ def tune(solvers, us, fs, ticks: int = 4, blocks=BLOCKS, coarse=COARSE, strips=S
         starts.append(w)
     table = []
 
-    def trial(cn, mb, sr, bn):
+    def trial(cn, mb, sr, bn, tc=0, zn=0):
         for s in solvers:
-            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn)
+            s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn, tile_config=tc,
+                     zsweep_n=zn)
         t = min(_time_ticks(solvers, starts, fs, ticks) for _ in range(2))
-        table.append((cn, mb, sr, bn, t))
+        table.append((cn, mb, sr, bn, tc, zn, t))
         if verbose:
             print(f"[tune] coarse_n={cn:2d} max_blocks={mb:6d} strip_rows={sr:4d} "
-                  f"block_n={bn:4d}: {1e3 * t:.3f} ms/tick", flush=True)
+                  f"block_n={bn:4d} tile_config={tc:2d} zsweep_n={zn:3d}: "
+                  f"{1e3 * t:.3f} ms/tick", flush=True)
         return t
 
     def best():
-        return min(table, key=lambda r: r[4])
+        return min(table, key=lambda r: r[6])
 
     for cn in coarse:
         for mb in blocks:
             trial(cn, mb, 0, 0)
-    cn, mb, _, _, _ = best()
+    cn, mb, _, _, _, _, _ = best()
     for sr in strips:
         trial(cn, mb, sr, 0)
-    cn, mb, sr, _, _ = best()
+    cn, mb, sr, _, _, _, _ = best()
     for bn in block_ns:
         trial(cn, mb, sr, bn)
-    cn, mb, sr, bn, t = best()
+    cn, mb, sr, bn, _, _, _ = best()
+    if bn != -1:
+        for tc in tiles:
+            trial(cn, mb, sr, bn, tc)
+    cn, mb, sr, bn, tc, _, _ = best()
+    for zn in zsweeps:
+        trial(cn, mb, sr, bn, tc, zn)
+    cn, mb, sr, bn, tc, zn, t = best()
     for s in solvers:
-        s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn)
-    return Choice(cn, mb, sr, bn, t, table)
+        s.retune(coarse_n=cn, max_blocks=mb, strip_rows=sr, block_n=bn, tile_config=tc,
+                 zsweep_n=zn)
+    return Choice(cn, mb, sr, bn, t, table, tc, zn)
 
 
 def load(path: str, k: str) -> dict | None:

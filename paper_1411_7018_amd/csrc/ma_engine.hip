@@ -1544,10 +1544,11 @@ bool Engine::block_level(int n, Mode mode) const
 // Automatic choice (zsweep_n = 0), from whole-solve timings on MI355X: the
 // z-stream sweep moves each node once per sweep but recomputes ~23% of the
 // updates and waits on its barriers, so it pays where the colour launches
-// are bound by their traffic and the update is cheap -- the linear
-// Poisson sweeps from n = 192 (about 150 against 200 us per sweep at
-// 257^3), the Monge-Ampere sweeps only from n = 320 (about 770 against 800
-// us per sweep at 385^3; slower at 257^3).
+// are bound by their traffic and the update is cheap -- the linear Poisson
+// sweeps from n = 256 (about 150 against 200 us per sweep at 257^3; at
+// n = 192 four colour launches take less than its 80 us) -- and the
+// Monge-Ampere sweeps only from n = 320 (766 against 800 us per sweep at
+// 385^3; slower at 257^3).
 bool Engine::zs_level(int n, Mode mode) const
 {
     if (order_ != MA_COLOR4 || smoother_ != MA_SMOOTHER_AUTO)
