@@ -33,7 +33,18 @@
  *   - coarsening continues while n is even and >= 4, so the coarsest grid
  *     has n = 2 (one unknown, the paper's h0 = 1/2) or n = 3;
  *   - the stopping rule is the relative discrete L2 residual of Section 4
- *     with r^0 the residual of the initial guess.
+ *     with r^0 the residual of the initial guess; a residual that stalls on
+ *     the round-off floor above the tolerance (three cycles in a row without
+ *     dropping below 0.9 x its best) ends the solve, not converged;
+ *   - the local root for F > 0 is the one below lambda_min (Theorem 2.2):
+ *     with q < 0 in the depressed cubic the three-root form is used even
+ *     when rounding leaves the discriminant at or just above zero (a double
+ *     smallest eigenvalue), where Cardano would give the largest root.
+ *
+ * Every function here is pinned by tests against values the paper prints,
+ * closed forms, invariants or brute force.  Not pinned: the per-cycle
+ * contraction and cycle counts of the 4-colour V-cycle ("parity unpinned":
+ * the paper reports lexicographic counts only).
  *
  * Compile: gcc -O2 -ffp-contract=off -fPIC -shared ma_oracle.c -lm
  */
