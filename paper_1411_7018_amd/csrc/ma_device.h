@@ -155,6 +155,18 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
     return sig;
 }
 
+// Newton start for a Hessian that is not SPD: a Gershgorin lower bound of
+// lambda_min minus F^{1/3}, where q >= 0.  Kept out of line: the compiler
+// would otherwise compute the cube root for every node ahead of the branch,
+// while nearly every node takes the SPD start sigma = 0.
+__device__ __noinline__ double gershgorin_start(Hess g, double F)
+{
+    const double lx = g.xx - (fabs(g.xy) + fabs(g.xz));
+    const double ly = g.yy - (fabs(g.xy) + fabs(g.yz));
+    const double lz = g.zz - (fabs(g.xz) + fabs(g.yz));
+    return fmin(lx, fmin(ly, lz)) - cbrt(F);
+}
+
 // Smallest real root sigma* of q(sig) = det(G - sig I) - F, which makes
 // G - sig* I the Hessian after the centre update u_p += sig* h^2 / 2.
 //
@@ -188,12 +200,8 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         return smallest_root_general(g, F);
     }
     double sig = 0.0;
-    if (!(g.xx > 0.0 && mab > 0.0 && I3 > 0.0)) {
-        const double lx = g.xx - (fabs(g.xy) + fabs(g.xz));
-        const double ly = g.yy - (fabs(g.xy) + fabs(g.yz));
-        const double lz = g.zz - (fabs(g.xz) + fabs(g.yz));
-        sig = fmin(lx, fmin(ly, lz)) - cbrt(F);
-    }
+    if (!(g.xx > 0.0 && mab > 0.0 && I3 > 0.0))
+        sig = gershgorin_start(g, F);
     const double c0 = I3 - F;
     const double thr = 1e-9 * (fabs(I1) + fabs(sig));
     double dprev = INFINITY;

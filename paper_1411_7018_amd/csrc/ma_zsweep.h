@@ -204,9 +204,16 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         if (!active(m, sp, P))
             return;
         const int io = lio[m][sp];
-        double *C = su + slot(P) + io;
-        const double *D = su + slot(P - 1) + io;
-        const double *U = su + slot(P + 1) + io;
+        // ring slots of planes P, P - 1, P + 1 from the step's slot (s mod R,
+        // uniform): P = s - 2c with 0 <= 2c <= 6 wraps at most once
+        const int rs = s % R;
+        int b = rs - 2 * c;
+        b += b < 0 ? R : 0;
+        const int bm = b == 0 ? R - 1 : b - 1;
+        const int bp = b == R - 1 ? 0 : b + 1;
+        double *C = su + b * PL + io;
+        const double *D = su + bm * PL + io;
+        const double *U = su + bp * PL + io;
         auto apply = [&](auto parity) {
             constexpr int odd = decltype(parity)::value;
             constexpr int xp = odd ? 1 - HW : HW;
