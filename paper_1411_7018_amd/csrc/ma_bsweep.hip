@@ -12,20 +12,61 @@ namespace {
 
 struct BCfg {
     int tx, ty, tz, nt;
-    int zwg;   // 0: block sweep; > 0: z-stream sweep aiming at about zwg workgroups
+    // z-stream sweeps: -1 chunks chosen by the model below, > 0 about zwg
+    // workgroups in all; 0: a block sweep
+    int zwg;
 };
 // Shapes (index = tile_config - 1).  Block sweeps: small blocks keep the
 // recomputation cheap in absolute terms and give many workgroups; more
 // threads per block cut the rounds of updates per phase, which is what a
 // sweep of a small grid waits on.  Z-stream sweeps (tz unused): TX x TY
 // columns whose update items (TX TY + 3 (TX + TY) + 14 per step) nearly
-// fill the workgroup once or twice; the planes are cut into chunks so that
-// a launch has about zwg workgroups (one per compute unit at a time, the
-// ring filling most of the LDS).
+// fill the workgroup once or twice; the planes are cut into chunks, by the
+// model of zs_chunks or into about zwg workgroups (one per compute unit at
+// a time, the ring filling most of the LDS).
 constexpr BCfg kCfg[] = {{8, 8, 8, 256, 0},   {8, 8, 8, 512, 0},  {8, 8, 8, 1024, 0},
                          {16, 8, 4, 256, 0},  {16, 16, 8, 512, 0}, {8, 8, 4, 512, 0},
-                         {8, 8, 4, 256, 0},   {32, 26, 0, 1024, 1536}, {32, 26, 0, 512, 1536},
-                         {32, 26, 0, 1024, 3072}, {40, 20, 0, 1024, 1536}};
+                         {8, 8, 4, 256, 0},   {32, 26, 0, 1024, -1}, {32, 26, 0, 512, -1},
+                         {32, 26, 0, 1024, 1536}, {40, 20, 0, 1024, -1}};
+
+// Compute units of the current device (one z-stream workgroup each at a time).
+int device_cus()
+{
+    static int cus = 0;
+    if (cus <= 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+// Chunks of a z-stream sweep over `cols` columns of an n grid: a chunk of zc
+// planes takes zc + 10 steps (the phases are skewed over 7 planes, plus the
+// pipeline's prefetch), and the workgroups run in rounds of one per compute
+// unit, so the sweep takes about ceil(cols * chunks / CUs) * (zc + 10) step
+// times; the chunk count minimising that (at least 16 planes a chunk).
+int zs_chunks(int n, int cols)
+{
+    const int cus = device_cus();
+    int best = 1;
+    long best_cost = -1;
+    for (int c = 1; c <= std::max(1, (n - 1) / 16); ++c) {
+        const int zc = zs_chunk(n, c);
+        const int t = (n - 1 + zc - 1) / zc;
+        const long rounds = (long(cols) * t + cus - 1) / cus;
+        const long cost = rounds * (zc + 10);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = t;
+        }
+    }
+    return best;
+}
 constexpr int kNumCfg = int(sizeof(kCfg) / sizeof(kCfg[0]));
 
 template <int OP, int TX, int TY, int NT>
@@ -150,11 +191,12 @@ void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *
     G->n = n;
     G->tiles_x = (n - 1 + b.tx - 1) / b.tx;
     G->tiles_y = (n - 1 + b.ty - 1) / b.ty;
-    if (b.zwg > 0) {
-        // chunks of at least 16 planes, about zwg workgroups in all; the
-        // last chunk takes what remains (none is empty)
+    if (b.zwg != 0) {
+        // chunks of at least 16 planes; the last chunk takes what remains
         const int cols = G->tiles_x * G->tiles_y;
-        int chunks = std::max(1, std::min((n - 1) / 16, (b.zwg + cols - 1) / cols));
+        const int chunks = b.zwg < 0 ? zs_chunks(n, cols)
+                                     : std::max(1, std::min((n - 1) / 16,
+                                                            (b.zwg + cols - 1) / cols));
         const int zc = zs_chunk(n, chunks);
         G->tiles_z = (n - 1 + zc - 1) / zc;
     } else {

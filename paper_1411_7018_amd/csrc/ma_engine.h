@@ -23,7 +23,7 @@ constexpr int kMaxGrids = 64;          // grids (solve, level) per batched launc
 // z-stream sweeps (ma_zsweep.h): first shape index among the block-sweep
 // configurations, and the smallest level that takes them when zsweep_n = 0
 constexpr int kZsFirstConfig = 7;
-constexpr int kZsweepAuto = 320;      // Monge-Ampere sweeps
+constexpr int kZsweepAuto = 256;      // Monge-Ampere sweeps
 constexpr int kZsweepAutoLap = 256;   // linear sweeps of the Poisson guess
 constexpr int kDefaultMaxBlocks = 16384;
 constexpr int kTailThreads = 512;      // threads of the coarse-level kernel

@@ -1543,12 +1543,10 @@ bool Engine::block_level(int n, Mode mode) const
 
 // Automatic choice (zsweep_n = 0), from whole-solve timings on MI355X: the
 // z-stream sweep moves each node once per sweep but recomputes ~23% of the
-// updates and waits on its barriers, so it pays where the colour launches
-// are bound by their traffic and the update is cheap -- the linear Poisson
-// sweeps from n = 256 (about 150 against 200 us per sweep at 257^3; at
-// n = 192 four colour launches take less than its 80 us) -- and the
-// Monge-Ampere sweeps only from n = 320 (766 against 800 us per sweep at
-// 385^3; slower at 257^3).
+// updates and waits on its barriers, and a grid needs enough 32 x 26
+// columns to give every compute unit a chunk of planes; it pays from
+// n = 256 (Monge-Ampere sweeps 169 against 201 us at 257^3 and 564 against
+// 801 us at 385^3, Poisson sweeps alike; at 129^3 51 against 36 us).
 bool Engine::zs_level(int n, Mode mode) const
 {
     if (order_ != MA_COLOR4 || smoother_ != MA_SMOOTHER_AUTO)
