@@ -115,6 +115,11 @@ typedef struct {
                               each workgroup walking a column of the grid plane
                               by plane, out of place) on levels with
                               n >= zsweep_n; 0 automatic, -1 never              */
+    int fuse_prolong;      /* FP64 levels with z-stream post-smoothing pairs:
+                              0 the first post-smoothing sweep also applies the
+                              coarse-grid correction (no separate prolongation
+                              pass; bitwise the same result), -1 separate
+                              prolongation pass                                */
 } ma_params;
 
 typedef struct {

@@ -36,7 +36,7 @@ class ma_params(ctypes.Structure):
                 ("tile_config", ctypes.c_int), ("block_n", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("coarse_n", ctypes.c_int),
                 ("max_blocks", ctypes.c_int), ("strip_rows", ctypes.c_int),
-                ("zsweep_n", ctypes.c_int)]
+                ("zsweep_n", ctypes.c_int), ("fuse_prolong", ctypes.c_int)]
 
 
 class ma2d_params(ctypes.Structure):

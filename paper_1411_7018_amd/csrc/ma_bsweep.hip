@@ -70,9 +70,12 @@ int zs_chunks(int n, int cols)
 constexpr int kNumCfg = int(sizeof(kCfg) / sizeof(kCfg[0]));
 
 template <int OP, int TX, int TY, int NT>
-hipError_t zgo_list(hipStream_t st, const FsList *L, int blocks, unsigned long long *nc)
+hipError_t zgo_list(hipStream_t st, const FsList *L, int blocks, unsigned long long *nc, bool pro)
 {
-    hipLaunchKernelGGL((k_zsweep<OP, TX, TY, NT>), dim3(blocks), dim3(NT), 0, st, L, nc);
+    if (pro)
+        hipLaunchKernelGGL((k_zsweep<OP, TX, TY, NT, true>), dim3(blocks), dim3(NT), 0, st, L, nc);
+    else
+        hipLaunchKernelGGL((k_zsweep<OP, TX, TY, NT, false>), dim3(blocks), dim3(NT), 0, st, L, nc);
     return hipGetLastError();
 }
 
@@ -100,8 +103,12 @@ hipError_t go_one(hipStream_t st, const FsGrid &G, unsigned long long *nc)
 }
 
 template <int OP>
-hipError_t list_op(int cfg, hipStream_t st, const FsList *L, int blocks, unsigned long long *nc)
+hipError_t list_op(int cfg, hipStream_t st, const FsList *L, int blocks, unsigned long long *nc,
+                   bool pro)
 {
+    // only the z-stream shapes prolong
+    if (pro && kCfg[cfg].zwg == 0)
+        return hipErrorInvalidValue;
     switch (cfg) {
     case 0:
         return go_list<OP, 8, 8, 8, 256>(st, L, blocks, nc);
@@ -119,11 +126,11 @@ hipError_t list_op(int cfg, hipStream_t st, const FsList *L, int blocks, unsigne
         return go_list<OP, 8, 8, 4, 256>(st, L, blocks, nc);
     case 7:
     case 9:
-        return zgo_list<OP, 32, 26, 1024>(st, L, blocks, nc);
+        return zgo_list<OP, 32, 26, 1024>(st, L, blocks, nc, pro);
     case 8:
-        return zgo_list<OP, 32, 26, 512>(st, L, blocks, nc);
+        return zgo_list<OP, 32, 26, 512>(st, L, blocks, nc, pro);
     case 10:
-        return zgo_list<OP, 40, 20, 1024>(st, L, blocks, nc);
+        return zgo_list<OP, 40, 20, 1024>(st, L, blocks, nc, pro);
     default:
         return hipErrorInvalidValue;
     }
@@ -207,16 +214,19 @@ void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *
     G->s = double(n) * double(n);
     G->s4 = 0.25 * G->s;
     G->hk = op == OP_MA ? 0.5 / G->s : 1.0 / (6.0 * G->s);
+    G->cu = G->cw = nullptr;
 }
 
+bool bsweep_is_zstream(int cfg) { return cfg >= 0 && cfg < kNumCfg && kCfg[cfg].zwg != 0; }
+
 hipError_t launch_bsweep(hipStream_t st, int op, int cfg, const FsList *L, int blocks,
-                         unsigned long long *nonconvex)
+                         unsigned long long *nonconvex, bool prolong)
 {
     if (cfg < 0 || cfg >= kNumCfg || blocks <= 0)
         return hipErrorInvalidValue;
     if (op == OP_MA)
-        return list_op<OP_MA>(cfg, st, L, blocks, nonconvex);
-    return list_op<OP_LAP>(cfg, st, L, blocks, nonconvex);
+        return list_op<OP_MA>(cfg, st, L, blocks, nonconvex, prolong);
+    return list_op<OP_LAP>(cfg, st, L, blocks, nonconvex, prolong);
 }
 
 hipError_t launch_bsweep_one(hipStream_t st, int op, int cfg, int n, const double *u_in,

@@ -111,7 +111,13 @@ __device__ __forceinline__ void shifted_cubic(const Hess &g, double F, double si
 // roots takes phi = (acos(.) + 2 pi)/3.  With a single real root the
 // hyperbolic form y = +-2 t cosh(acosh|.|/3) applies.  Two Newton steps on
 // the shifted form then polish the result, each kept only if |q| drops.
-__device__ __noinline__ double smallest_root_general(Hess g, double F)
+//
+// The closed form and the polishing steps are two out-of-line functions,
+// each with few values live: a call counts its callee's registers against
+// the calling kernel, and one body holding the Hessian across the
+// transcendental functions would take more registers than the colour-sweep
+// kernels may hold at eight waves per SIMD.
+__device__ __noinline__ double general_start(Hess g, double F)
 {
     const double m = (g.xx + g.yy + g.zz) * (1.0 / 3.0);
     const double a = g.xx - m, b = g.yy - m, c = g.zz - m;
@@ -138,7 +144,12 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
     } else {
         y = cbrt(-Q);
     }
-    double sig = y + m, q, dq;
+    return y + m;
+}
+
+__device__ __noinline__ double general_polish(Hess g, double F, double sig)
+{
+    double q, dq;
     shifted_cubic(g, F, sig, q, dq);
     for (int it = 0; it < 2; ++it) {
         if (!(dq != 0.0))
@@ -153,6 +164,11 @@ __device__ __noinline__ double smallest_root_general(Hess g, double F)
         dq = dqc;
     }
     return sig;
+}
+
+__device__ __forceinline__ double smallest_root_general(const Hess &g, double F)
+{
+    return general_polish(g, F, general_start(g, F));
 }
 
 // Newton start for a Hessian that is not SPD: a Gershgorin lower bound of

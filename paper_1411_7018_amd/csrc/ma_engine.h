@@ -20,6 +20,9 @@
 namespace mafas {
 
 constexpr int kMaxGrids = 64;          // grids (solve, level) per batched launch
+// Sums of squares per slot held by the pinned norm ring: one per tick in
+// flight (at most two queued entries of at most two ticks each).
+constexpr int kNormRing = 4;
 // z-stream sweeps (ma_zsweep.h): first shape index among the block-sweep
 // configurations, and the smallest level that takes them when zsweep_n = 0
 constexpr int kZsFirstConfig = 7;
@@ -175,9 +178,13 @@ hipError_t launch_arm(hipStream_t st, const ArmSet &a, double *thr, char *base,
 double sum_threshold(double c, int n);
 // fs = F in the order of the 4-colour sweep rows of an n grid (ma_solver::fs)
 hipError_t launch_fsplit(hipStream_t st, int n, const double *F, double *fs, long cs);
-// block sweeps of an FsList (ma_fsweep.h): cfg block shape, blocks >= tiles
+// block sweeps of an FsList (ma_fsweep.h): cfg block shape, blocks >= tiles;
+// prolong: a z-stream shape whose grids carry the coarse u and w (cu, cw)
+// and add the interpolated coarse correction to u_in as they read it
 hipError_t launch_bsweep(hipStream_t st, int op, int cfg, const FsList *L, int blocks,
-                         unsigned long long *nonconvex);
+                         unsigned long long *nonconvex, bool prolong = false);
+// whether block shape cfg is a z-stream shape
+bool bsweep_is_zstream(int cfg);
 void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *F, int op,
                  int slot, FsGrid *G);
 // one workgroup per TailList entry (blocks >= entries); mode: Engine::Mode
@@ -225,9 +232,13 @@ class Engine {
     // idle while the host reads the norms; a later tick_ahead call with
     // these solves consumes it, and a solve that stopped skips it on the
     // device.  The caller queues ahead only while no solve can stop for a
-    // reason the device does not see (a cycle limit).
+    // reason the device does not see (a cycle limit).  pair: what is queued
+    // ahead may be two ticks in one graph (one graph boundary instead of
+    // two), or one tick behind such a pair while its first tick is read; the
+    // caller asks for it only while no solve can stop for such a reason at
+    // the tick read now or the next.
     ma_status tick_ahead(Mode mode, const std::vector<char> &active, const std::vector<double> &thr,
-                         bool ahead, std::vector<double> &norms);
+                         bool ahead, std::vector<double> &norms, bool pair = false);
     // Wait for ticks still queued ahead (each solve in them must have stopped).
     ma_status settle();
     // Ticks queued and not yet read.
@@ -267,7 +278,7 @@ class Engine {
   private:
     ma_status rebuild(Mode mode, const std::vector<char> &active);
     ma_status enqueue(Mode mode, bool cycle);
-    ma_status launch(Mode mode, bool cycle, const std::vector<char> &active);
+    ma_status launch(Mode mode, bool cycle, const std::vector<char> &active, int ticks = 1);
     ma_status collect(std::vector<double> &norms);
     ma_status plain(Mode mode, bool cycle, const std::vector<char> &active,
                     std::vector<double> &norms);
@@ -281,7 +292,7 @@ class Engine {
     GridItem grid(int kind, int i, int l, Mode mode) const;
     int levels(int i) const;
     int multiblock_levels(int i) const;  // leading levels with n > coarse_n
-    ma_status capture(int slot, Mode mode);
+    ma_status capture(int slot, Mode mode, int ticks);
     std::vector<int> shape() const;
     ma_status prof_mark();
 
@@ -296,6 +307,7 @@ class Engine {
     int nu1_ = 2, nu2_ = 2, nu0_ = 1, order_ = 0, rmode_ = 0, inner_ = 2;
     int coarse_n_ = 16, max_blocks_ = kDefaultMaxBlocks, strip_rows_ = 0;
     int smoother_ = MA_SMOOTHER_AUTO, tile_config_ = 0, block_n_ = 0, zsweep_n_ = 0;
+    bool fuse_prolong_ = true;
     int strip_width(int gy) const;
     // sweeps of a multi-block n grid as block sweeps, and among them as
     // z-stream sweeps (the mode sets the automatic choice)
@@ -323,6 +335,8 @@ class Engine {
     std::vector<size_t> fsoff_;            // byte offset of each FsList
     std::vector<int> fsblocks_;            // blocks per FsList launch (0: no grid)
     std::vector<int> fscfg_;               // block shape per FsList
+    std::vector<char> fspro_;              // the FsList's sweep also prolongs
+    std::vector<char> pro_fused_;          // [depth] prolongation inside the up-leg's first sweep
     size_t fs_stride_ = 0;
     std::vector<int> res_, rst_, pro_, inj_;
     std::vector<const double *> fs_src_;   // right-hand side held in each solve's fs
@@ -336,8 +350,8 @@ class Engine {
     double *partials_ = nullptr;
     size_t partials_cap_ = 0;
     // Norm ring (k_batched_reduce): hnorm_ / hstamp_ pinned coherent host
-    // memory, 2 * kMaxGrids entries each, dnorm_ / dstamp_ their device
-    // aliases; dseq_, dthr_ per-slot device state.
+    // memory, kNormRing * kMaxGrids entries each, dnorm_ / dstamp_ their
+    // device aliases; dseq_, dthr_ per-slot device state.
     double *dnorm_ = nullptr, *hnorm_ = nullptr;
     unsigned *dstamp_ = nullptr, *hstamp_ = nullptr, *dseq_ = nullptr;
     double *dthr_ = nullptr;
@@ -349,13 +363,22 @@ class Engine {
     std::vector<char> halted_ = std::vector<char>(kMaxGrids, 0);
     std::vector<char> armq_ = std::vector<char>(kMaxGrids, 0);
     std::vector<double> armv_ = std::vector<double>(kMaxGrids, -1.0);
-    // queued ticks, oldest first, and spare events
+    // queued entries (one graph of one or two ticks), oldest first, and
+    // spare events.  When an entry's event has completed, the ring entries
+    // its ticks may have written are copied out (sum[j * kMaxGrids + i],
+    // stamp likewise, for its tick j and slot i): a later entry may reuse
+    // them before the host has read the entry's last tick.
     struct Pending {
         Mode mode;
         bool cycle;
         std::vector<char> active;
         hipEvent_t ev;
-        size_t nev;  // profile events recorded by the tick
+        size_t nev;     // profile events recorded by the tick
+        int ticks = 1;  // ticks in the entry
+        int done = 0;   // ticks the host has read
+        bool synced = false;
+        std::vector<double> sum;
+        std::vector<unsigned> stamp;
     };
     std::deque<Pending> fifo_;
     std::vector<hipEvent_t> evpool_;
@@ -367,10 +390,11 @@ class Engine {
     bool built_ = false;
     // Captured ticks, one slot per mode; slot mode + 3 is the profiled form:
     // the tick split into segments at the finest-level sweep boundaries, so
-    // the timing events are recorded on the stream between segment launches.
-    // A graph is replayed only while the launch shapes it was captured with
-    // (depths, list table address and stride, blocks per launch) still hold.
-    static constexpr int kSlots = 6;
+    // the timing events are recorded on the stream between segment launches;
+    // slot mode + 6 is two ticks in one graph.  A graph is replayed only
+    // while the launch shapes it was captured with (depths, list table
+    // address and stride, blocks per launch) still hold.
+    static constexpr int kSlots = 9;
     std::vector<hipGraphExec_t> gseg_[kSlots];
     std::vector<int> graph_shape_[kSlots];
     const char *graph_dl_[kSlots] = {};

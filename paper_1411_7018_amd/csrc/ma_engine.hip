@@ -413,19 +413,31 @@ __device__ __forceinline__ void run_item(const GridItem &G, int bx, int by, int 
                 for (int dx = -1; dx <= 1; ++dx)
                     P[(dy + 1) * 3 + (dx + 1)] = u[b0 + dx + sy * dy];
         };
+        // the next plane's loads are issued before this plane's residual,
+        // so each iteration's arithmetic overlaps the loads of the next
+        double P3[9];
         load(P0, k0 - 1);
         load(P1, k0);
+        load(P2, k0 + 1);   // k0 + 1 <= k1 <= n
+        double fc = F[ic + sy * j + sz * k0];
         double acc = 0.0;
         for (int k = k0; k < k1; ++k) {
-            load(P2, k + 1);
-            const double rv = resid_win<OP>(P0 + 4, P1 + 4, P2 + 4, G.s, F[ic + sy * j + sz * k]);
+            double fn = 0.0;
+            const bool more = k + 1 < k1;   // uniform across the wavefront
+            if (more) {
+                load(P3, k + 2);
+                fn = F[ic + sy * j + sz * (k + 1)];
+            }
+            const double rv = resid_win<OP>(P0 + 4, P1 + 4, P2 + 4, G.s, fc);
             if (i <= n - 1)
                 acc += rv * rv;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 P0[q] = P1[q];
                 P1[q] = P2[q];
+                P2[q] = P3[q];
             }
+            fc = fn;
         }
         const double sum = wave_sum64(acc);
         if (t == 0)
@@ -554,7 +566,7 @@ __global__ __launch_bounds__(64) void k_fsplit(int n, const double *__restrict__
 // partials t, t + 1024, ... in order, then a fixed shuffle tree per wave and
 // the 16 wave sums in order.  The sum of solve `slot` goes to the pinned
 // host ring R: the k-th sum of a slot (k = R.seq[slot], counted on the
-// device) lands in entry k & 1 with its k stamped beside it.  When the
+// device) lands in entry k mod kNormRing with its k stamped beside it.  When the
 // slot's threshold is armed (thr >= 0), a sum at or below it, or one that is
 // not finite, means the host's stopping test has passed: the slot's bit is
 // set in the stopped mask of every list header, and the ticks already
@@ -597,7 +609,7 @@ __global__ __launch_bounds__(1024) void k_batched_reduce(const BatchList *__rest
             s += part[w];
         const int slot = G.slot;
         const unsigned k = R.seq[slot];
-        const int e = int(k & 1u) * kMaxGrids + slot;
+        const int e = int(k % unsigned(kNormRing)) * kMaxGrids + slot;
         R.sum[e] = s;
         R.stamp[e] = k;
         R.seq[slot] = k + 1u;
@@ -1367,11 +1379,13 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
                  p.inner_cycles != p0->inner_cycles || p.coarse_n != p0->coarse_n ||
                  p.max_blocks != p0->max_blocks || p.strip_rows != p0->strip_rows ||
                  p.smoother != p0->smoother || p.tile_config != p0->tile_config ||
-                 p.block_n != p0->block_n || p.zsweep_n != p0->zsweep_n)
+                 p.block_n != p0->block_n || p.zsweep_n != p0->zsweep_n ||
+                 p.fuse_prolong != p0->fuse_prolong)
             return fail(MA_ERR_ARG,
                         "solvers in one batch must share smoothing counts, ordering, "
                         "restriction, precision, inner cycles, coarse_n, max_blocks, "
-                        "strip_rows, smoother, tile_config, block_n and zsweep_n");
+                        "strip_rows, smoother, tile_config, block_n, zsweep_n and "
+                        "fuse_prolong");
     }
     if (!p0)
         return fail(MA_ERR_ARG, "a batch needs at least one solver");
@@ -1402,6 +1416,7 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
     tile_config_ = p0->tile_config;
     block_n_ = p0->block_n;
     zsweep_n_ = p0->zsweep_n;
+    fuse_prolong_ = p0->fuse_prolong == 0;
     built_ = false;
     if (!stream_) {
         E_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
@@ -1412,13 +1427,15 @@ ma_status Engine::set(const std::vector<SolveRef> &solves, hipStream_t user, boo
         // The reduction kernel writes each tick's sums straight into these
         // pinned, coherent host buffers: no copy is queued after a tick, and
         // the host reads them once the tick's event has completed.
-        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_), 2 * kMaxGrids * sizeof(double),
+        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hnorm_),
+                            kNormRing * kMaxGrids * sizeof(double),
                             hipHostMallocMapped | hipHostMallocCoherent));
         E_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dnorm_), hnorm_, 0));
-        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstamp_), 2 * kMaxGrids * sizeof(unsigned),
+        E_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstamp_),
+                            kNormRing * kMaxGrids * sizeof(unsigned),
                             hipHostMallocMapped | hipHostMallocCoherent));
         E_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&dstamp_), hstamp_, 0));
-        for (int e = 0; e < 2 * kMaxGrids; ++e)
+        for (int e = 0; e < kNormRing * kMaxGrids; ++e)
             hstamp_[e] = ~0u;
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dseq_), kMaxGrids * sizeof(unsigned)));
         E_HIP(hipMalloc(reinterpret_cast<void **>(&dthr_), kMaxGrids * sizeof(double)));
@@ -1853,6 +1870,8 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
     fsoff_.clear();
     fsblocks_.clear();
     fscfg_.clear();
+    fspro_.clear();
+    pro_fused_.assign(D_, 0);
     fs_stride_ = fs_list_bytes(S);
     bsd_.assign(D_, std::vector<int>());
     bsu_.assign(D_, std::vector<int>());
@@ -1884,7 +1903,10 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             else
                 cfg = bsweep_pick(nmax, tiles8);
             auto has = [&](int i) { return solves_[i].s && multiblock_levels(i) > d; };
-            auto pairs = [&](int nsw, auto count, std::vector<int> &out) {
+            // up: the post-smoothing pairs, whose first z-stream sweep also
+            // applies the coarse-grid correction (the solves in it are those
+            // of the depth's prolongation list: a coarser level, nu2 > 0)
+            auto pairs = [&](int nsw, auto count, std::vector<int> &out, bool up) {
                 out.assign(nsw, -1);
                 if (!blk)
                     return;
@@ -1895,6 +1917,9 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                             same = (count(i) > k) == (count(i) > k + 1);
                     if (!same)
                         continue;
+                    const bool pro = up && k == 0 && fuse_prolong_ && bsweep_is_zstream(cfg);
+                    if (pro)
+                        pro_fused_[d] = 1;
                     out[k] = int(fsoff_.size());
                     for (int half = 0; half < 2; ++half) {
                         FsList L;
@@ -1911,6 +1936,10 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                             FsGrid G;
                             bsweep_grid(cfg, sv->lv[d].n, half ? t : u, half ? u : t,
                                         level_F(i, d, mode), op, i, &G);
+                            if (pro && half == 0) {
+                                G.cu = sv->lv[d + 1].u;
+                                G.cw = sv->lv[d + 1].w;
+                            }
                             const int tiles = G.tiles_x * G.tiles_y * G.tiles_z;
                             bound += tiles;
                             if (!active[i])
@@ -1924,15 +1953,16 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                         fsoff_.push_back(off);
                         fsblocks_.push_back(int(bound));
                         fscfg_.push_back(cfg);
+                        fspro_.push_back(pro && half == 0 ? 1 : 0);
                         hbuf_.resize(off + fs_stride_, 0);
                         std::memcpy(hbuf_.data() + off, &L, fs_list_bytes(L.ngrids));
                     }
                 }
             };
             pairs(int(swd_[d].size()),
-                  [&](int i) { return d < levels(i) - 1 ? nu1_ : nu0_; }, bsd_[d]);
+                  [&](int i) { return d < levels(i) - 1 ? nu1_ : nu0_; }, bsd_[d], false);
             pairs(int(swu_[d].size()), [&](int i) { return d < levels(i) - 1 ? nu2_ : 0; },
-                  bsu_[d]);
+                  bsu_[d], true);
         }
     }
 
@@ -2009,6 +2039,9 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
             const int sweeps = single ? nu0_ : nu1_ + nu2_;
             const int reps = mixed ? inner_ : 1;
             prof_bytes_tick_ += reps * sweeps * (mixed ? 20.0 : 24.0) * in;
+            // a sweep that also prolongs reads the coarse u and w
+            if (D_ > 0 && pro_fused_[0] && !single)
+                prof_bytes_tick_ += 16.0 * double(npts(solves_[i].s->lv[1].n));
         }
     if (D_ > 0) {
         const int reps = mixed ? inner_ : 1;
@@ -2106,7 +2139,8 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
                 for (int h = 0; h < 2; ++h) {
                     const int f = pairs[k] + h;
                     if (fsblocks_[f] > 0)
-                        E_HIP(launch_bsweep(stream_, op, fscfg_[f], FL(f), fsblocks_[f], dcount_));
+                        E_HIP(launch_bsweep(stream_, op, fscfg_[f], FL(f), fsblocks_[f], dcount_,
+                                            fspro_[f] != 0));
                 }
                 k += 2;
             } else {
@@ -2142,7 +2176,9 @@ ma_status Engine::enqueue(Mode mode, bool cycle)
                               reinterpret_cast<const TailList *>(dl_ + toff_), tail_blocks_, nu1_,
                               nu2_, nu0_, dcount_, dfall_));
         for (int d = D_ - 1; d >= 0; --d) {
-            MA_TRY(go(mixed ? LK_MPROLONG : LK_PROLONG, pro_[d], 0));
+            // a fused depth prolongs inside its first post-smoothing sweep
+            if (!pro_fused_[d])
+                MA_TRY(go(mixed ? LK_MPROLONG : LK_PROLONG, pro_[d], 0));
             if (profile_ && d == 0)
                 MA_TRY(prof_mark());
             MA_TRY(sweeps(swu_[d], bsu_[d]));
@@ -2191,6 +2227,8 @@ std::vector<int> Engine::shape() const
     s.push_back(int(fs_stride_));
     s.insert(s.end(), fsblocks_.begin(), fsblocks_.end());
     s.insert(s.end(), fscfg_.begin(), fscfg_.end());
+    s.insert(s.end(), fspro_.begin(), fspro_.end());
+    s.insert(s.end(), pro_fused_.begin(), pro_fused_.end());
     s.push_back(int(rroff_.size()));
     s.push_back(rroff_.empty() ? 0 : int(rroff_[0]));
     s.insert(s.end(), rrblocks_.begin(), rrblocks_.end());
@@ -2200,11 +2238,14 @@ std::vector<int> Engine::shape() const
 }
 
 // Queue one tick (cycle) or one norm evaluation of the active solves on the
-// engine stream, followed by an event; the host waits in collect().
-ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
+// engine stream, followed by an event; the host waits in collect().  ticks =
+// 2 queues two cycles as one entry (one graph when graphs are on).
+ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active, int ticks)
 {
     if (active.size() != solves_.size())
         return fail(MA_ERR_ARG, "active mask size");
+    if (ticks < 1 || ticks > 2 || (ticks == 2 && (!cycle || profile_)))
+        return fail(MA_ERR_ARG, "internal: ticks per launch");
     if (!built_ || mode != built_mode_ || active != built_active_) {
         if (!fifo_.empty())
             return fail(MA_ERR_DEVICE, "internal: list rebuild with ticks in flight");
@@ -2218,11 +2259,11 @@ ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
     }
     if (cycle)
         MA_TRY(refresh_fs(mode, active));
-    const int m = int(mode) + (profile_ ? 3 : 0);
+    const int m = int(mode) + (profile_ ? 3 : 0) + (ticks == 2 ? 6 : 0);
     size_t nev = 0;
     if (cycle && graphs_) {
         if (gseg_[m].empty() || graph_dl_[m] != dl_ || graph_shape_[m] != shape())
-            MA_TRY(capture(m, mode));
+            MA_TRY(capture(m, mode, ticks));
         // segment k is followed by timing event k (profiled form only)
         const size_t ns = gseg_[m].size();
         while (pev_.size() + 1 < ns) {
@@ -2239,7 +2280,8 @@ ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
         nev = ns - 1;
     } else {
         pev_used_ = 0;
-        MA_TRY(enqueue(mode, cycle));
+        for (int t = 0; t < ticks; ++t)
+            MA_TRY(enqueue(mode, cycle));
         nev = pev_used_;
     }
     hipEvent_t ev = nullptr;
@@ -2254,40 +2296,67 @@ ma_status Engine::launch(Mode mode, bool cycle, const std::vector<char> &active)
         (void)hipEventDestroy(ev);
         return fail(MA_ERR_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(er));
     }
-    fifo_.push_back(Pending{mode, cycle, active, ev, nev});
+    Pending p;
+    p.mode = mode;
+    p.cycle = cycle;
+    p.active = active;
+    p.ev = ev;
+    p.nev = nev;
+    p.ticks = ticks;
+    fifo_.push_back(std::move(p));
     return MA_OK;
 }
 
-// Wait for the oldest queued tick and read the norms of the solves it ran
-// (those not halted before it).  The sum of a slot is the next entry of its
-// ring; a stamp that disagrees with the host's count means the host and the
-// device disagree on which ticks ran, and fails.
+// Wait for the oldest queued entry (unless an earlier call did) and read
+// the norms of its next tick for the solves that tick ran (those not halted
+// before it).  The sum of a slot is the next entry of its ring; a stamp that
+// disagrees with the host's count means the host and the device disagree on
+// which ticks ran, and fails.
 ma_status Engine::collect(std::vector<double> &norms)
 {
     if (fifo_.empty())
         return fail(MA_ERR_DEVICE, "internal: no tick to collect");
-    Pending p = std::move(fifo_.front());
-    fifo_.pop_front();
-    const hipError_t er = hipEventSynchronize(p.ev);
-    evpool_.push_back(p.ev);
-    if (er != hipSuccess)
-        return fail(MA_ERR_DEVICE, std::string("tick: ") + hipGetErrorString(er));
+    Pending &p = fifo_.front();
+    if (!p.synced) {
+        const hipError_t er = hipEventSynchronize(p.ev);
+        if (er != hipSuccess) {
+            evpool_.push_back(p.ev);
+            fifo_.pop_front();
+            return fail(MA_ERR_DEVICE, std::string("tick: ") + hipGetErrorString(er));
+        }
+        p.synced = true;
+        // the ring entries the entry's ticks may have written, before a
+        // later entry can reuse them
+        p.sum.assign(size_t(p.ticks) * kMaxGrids, 0.0);
+        p.stamp.assign(size_t(p.ticks) * kMaxGrids, ~0u);
+        for (size_t i = 0; i < solves_.size(); ++i) {
+            if (!solves_[i].s || !p.active[i] || halted_[i])
+                continue;
+            for (int t = 0; t < p.ticks; ++t) {
+                const unsigned k = seq_[i] + unsigned(t);
+                const size_t e = size_t(k % unsigned(kNormRing)) * kMaxGrids + i;
+                p.sum[size_t(t) * kMaxGrids + i] = hnorm_[e];
+                p.stamp[size_t(t) * kMaxGrids + i] = hstamp_[e];
+            }
+        }
+    }
+    const int t = p.done;
     norms.resize(solves_.size());
     for (size_t i = 0; i < solves_.size(); ++i) {
         if (!solves_[i].s || !p.active[i] || halted_[i])
             continue;
         const unsigned k = seq_[i];
-        const size_t e = size_t(k & 1u) * kMaxGrids + i;
-        if (hstamp_[e] != k)
+        const size_t e = size_t(t) * kMaxGrids + i;
+        if (p.stamp[e] != k)
             return fail(MA_ERR_DEVICE, "internal: norm ring out of step with the host");
-        const double raw = hnorm_[e];
+        const double raw = p.sum[e];
         seq_[i] = k + 1u;
         const int n = solves_[i].s->p.n;
         const double h = 1.0 / double(n);
         norms[i] = std::sqrt(raw * h * h * h);
         // the device's decision in k_batched_reduce, on the same values
-        const double t = thr_dev_[i];
-        if (t >= 0.0 && (raw <= t || !std::isfinite(raw)))
+        const double th = thr_dev_[i];
+        if (th >= 0.0 && (raw <= th || !std::isfinite(raw)))
             halted_[i] = 1;
     }
     if (profile_ && p.cycle) {
@@ -2298,6 +2367,10 @@ ma_status Engine::collect(std::vector<double> &norms)
         }
         prof_bytes_ += prof_bytes_tick_;
         prof_launches_ += prof_launches_tick_;
+    }
+    if (++p.done == p.ticks) {
+        evpool_.push_back(p.ev);
+        fifo_.pop_front();
     }
     return MA_OK;
 }
@@ -2310,7 +2383,9 @@ ma_status Engine::settle()
     while (!fifo_.empty()) {
         Pending p = std::move(fifo_.front());
         fifo_.pop_front();
-        const hipError_t er = hipEventSynchronize(p.ev);
+        hipError_t er = hipSuccess;
+        if (!p.synced)
+            er = hipEventSynchronize(p.ev);
         evpool_.push_back(p.ev);
         if (er != hipSuccess)
             return fail(MA_ERR_DEVICE, std::string("tick: ") + hipGetErrorString(er));
@@ -2423,7 +2498,7 @@ ma_status Engine::plain(Mode mode, bool cycle, const std::vector<char> &active,
 
 ma_status Engine::tick_ahead(Mode mode, const std::vector<char> &active,
                              const std::vector<double> &thr, bool ahead,
-                             std::vector<double> &norms)
+                             std::vector<double> &norms, bool pair)
 {
     if (active.size() != solves_.size() || thr.size() != solves_.size())
         return fail(MA_ERR_ARG, "active mask size");
@@ -2447,16 +2522,28 @@ ma_status Engine::tick_ahead(Mode mode, const std::vector<char> &active,
         armed |= armq_[i] != 0;
     if (armed)
         return fail(MA_ERR_DEVICE, "internal: thresholds changed with ticks in flight");
-    if (ahead && !profile_ && fifo_.size() == 1 && built_ && built_mode_ == mode &&
-        built_active_ == active)
-        MA_TRY(launch(mode, true, active));
+    // Queue ahead so that the device has a tick to run while the host reads
+    // this one: when the tick read now is the last one queued, one tick or
+    // (pair) two in one graph; when it is the first of two in one graph,
+    // one tick behind them, which the pair condition allows (no stop the
+    // device does not see at this tick or the next).  At most two entries
+    // of at most two ticks each are ever queued, as the ring requires.
+    if (!profile_ && fifo_.size() == 1 && built_ && built_mode_ == mode &&
+        built_active_ == active) {
+        const int rem = fifo_.front().ticks - fifo_.front().done;
+        if (rem == 1 && ahead)
+            MA_TRY(launch(mode, true, active, pair ? 2 : 1));
+        else if (rem == 2 && ahead && pair)
+            MA_TRY(launch(mode, true, active, 1));
+    }
     return collect(norms);
 }
 
-// Capture one tick of mode into slot m: one graph, or (profiled form) one
-// graph per segment between the finest-level sweep boundaries.  A segment
-// with no work is kept as a null entry so the event order is unchanged.
-ma_status Engine::capture(int m, Mode mode)
+// Capture ticks (1 or 2) ticks of mode into slot m: one graph, or
+// (profiled form, one tick) one graph per segment between the finest-level
+// sweep boundaries.  A segment with no work is kept as a null entry so the
+// event order is unchanged.
+ma_status Engine::capture(int m, Mode mode, int ticks)
 {
     for (hipGraphExec_t x : gseg_[m])
         if (x)
@@ -2468,7 +2555,9 @@ ma_status Engine::capture(int m, Mode mode)
     pev_used_ = 0;
     seg_capture_ = profile_;
     E_HIP(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
-    const ma_status st = enqueue(mode, true);
+    ma_status st = MA_OK;
+    for (int t = 0; t < ticks && st == MA_OK; ++t)
+        st = enqueue(mode, true);
     hipGraph_t last = nullptr;
     const hipError_t ec = hipStreamEndCapture(stream_, &last);
     seg_capture_ = false;

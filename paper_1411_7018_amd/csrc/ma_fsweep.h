@@ -48,6 +48,10 @@ struct FsGrid {
     int slot;       // counter slot of the solve
     double s, s4;   // 1/h^2, 1/(4h^2)
     double hk;      // h^2/2 (nonlinear update) or 1/(6s) (linear update)
+    // z-stream sweeps that also prolong (the first sweep after the coarse
+    // correction): the coarse level's u and w, whose difference is
+    // interpolated onto u_in as it is read; null otherwise
+    const double *cu, *cw;
 };
 
 constexpr int kFsMaxGrids = 64;

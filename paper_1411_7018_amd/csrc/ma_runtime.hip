@@ -76,6 +76,10 @@ bool valid_params(const ma_params *p, std::string &why)
         why = "zsweep_n must be in -1..2048";
         return false;
     }
+    if (p->fuse_prolong != 0 && p->fuse_prolong != -1) {
+        why = "fuse_prolong must be 0 or -1";
+        return false;
+    }
     if (p->graphs != 0 && p->graphs != 1) {
         why = "graphs must be 0 or 1";
         return false;
@@ -628,6 +632,7 @@ ma_solver *ma_solver::view(int l)
     views[l]->p.strip_rows = p.strip_rows;
     views[l]->p.block_n = p.block_n;
     views[l]->p.zsweep_n = p.zsweep_n;
+    views[l]->p.fuse_prolong = p.fuse_prolong;
     views[l]->p.tile_config = p.tile_config;
     return views[l];
 }
@@ -773,11 +778,19 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
         const double rho = st->prev > 0.0 ? st->last / st->prev : 0.1;
         return st->last * rho > 8.0 * c;
     };
+    // The same guess one tick further: what is queued ahead may be two ticks
+    // in one graph (one graph boundary fewer) when the solve is guessed to
+    // go on after the tick following the one being read as well.
+    auto goes_on2 = [](const SolveState *st, double c) {
+        const double rho = st->prev > 0.0 ? st->last / st->prev : 0.1;
+        return st->last * rho * rho > 8.0 * c;
+    };
     // 2. one linear V-cycle of the Poisson guess
     bool init_ahead = false;
     if (select(SolveState::INIT)) {
         std::vector<double> thr(S, -1.0);
         bool spec = ahead && only(SolveState::INIT);
+        bool pair = spec;
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 const ma_params &p = eng.ref(i).s->p;
@@ -785,8 +798,10 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 thr[i] = sum_threshold(c, p.n);
                 spec &= states[i]->rep.init_cycles + 2 <= p.init_max_cycles &&
                         goes_on(states[i], c);
+                pair &= states[i]->rep.init_cycles + 3 <= p.init_max_cycles &&
+                        goes_on2(states[i], c);
             }
-        MA_TRY(eng.tick_ahead(Engine::MODE_LAP, act, thr, spec, nrm));
+        MA_TRY(eng.tick_ahead(Engine::MODE_LAP, act, thr, spec, nrm, spec && pair));
         init_ahead = eng.pending() > 0;
         for (int i = 0; i < S; ++i)
             if (act[i]) {
@@ -866,6 +881,7 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
     if (select(SolveState::MAIN)) {
         std::vector<double> thr(S, -1.0);
         bool spec = ahead && only(SolveState::MAIN);
+        bool pair = spec;
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 const ma_params &p = eng.ref(i).s->p;
@@ -877,8 +893,10 @@ ma_status mafas::drive_step(Engine &eng, std::vector<SolveState *> &states, bool
                 // of one that could make it
                 spec &= done + 2 <= p.max_cycles && goes_on(states[i], c) &&
                         states[i]->stall + 1 < 3;
+                pair &= done + 3 <= p.max_cycles && goes_on2(states[i], c) &&
+                        states[i]->stall + 2 < 3;
             }
-        MA_TRY(eng.tick_ahead(main_mode, act, thr, spec, nrm));
+        MA_TRY(eng.tick_ahead(main_mode, act, thr, spec, nrm, spec && pair));
         for (int i = 0; i < S; ++i)
             if (act[i]) {
                 SolveState *st = states[i];

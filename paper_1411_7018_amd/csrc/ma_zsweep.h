@@ -33,6 +33,18 @@
 // ma_device.h) on the same values as in the colour-phase kernels, so the
 // result is bitwise identical to four colour phases.  Algorithmic bytes
 // per interior node and sweep: read u 8, read F 8, write u 8.
+//
+// The first sweep after a coarse-grid correction can also prolong it (PRO):
+// u_in then holds u before the correction, and each interior value is
+// corrected as it enters the ring by the trilinear interpolation of the
+// coarse e = u_H - w_H (Algorithm 1's correction step), summed in the order
+// of the prolongation kernels, so u_in + P e is bitwise the prolonged u they
+// write.  The coarse e of the column's footprint goes through a second LDS
+// ring of four coarse planes: coarse plane K is loaded at step 2K - 6,
+// written to the ring at step 2K - 4 and read by the fine planes 2K - 1 ..
+// 2K + 1 as they enter the fine ring at steps 2K - 3 .. 2K - 1.  The
+// separate prolongation pass (read and write u once more) goes away; the
+// fused sweep reads 16 bytes more per coarse node.
 #pragma once
 
 #include "ma_fsweep.h"
@@ -69,6 +81,11 @@ struct ZsShape {
     }
     static constexpr int items = first(3) + count(3);
     static constexpr size_t lds_bytes() { return size_t(NL) * sizeof(double); }
+    // coarse-correction ring of a prolonging sweep: the footprint's first
+    // x is odd (1 + tx TX - H), so its coarse nodes span LX / 2 + 2 columns
+    // and LY / 2 + 2 rows
+    static constexpr int CX = LX / 2 + 2, CY = LY / 2 + 2, CPL = CX * CY, CR = 4;
+    static constexpr int NLP = NL + CR * CPL;
     static_assert(TX % 2 == 0 && TY % 2 == 0, "TX and TY must be even");
 };
 
@@ -80,7 +97,7 @@ __host__ __device__ inline int zs_chunk(int n, int chunks)
 
 // Column `tile` of grid G by a workgroup of NT threads; su: LDS.  Global
 // offsets are 32-bit: grids up to n = 1289.
-template <int OP, int TX, int TY, int NT>
+template <int OP, int TX, int TY, int NT, bool PRO>
 __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *__restrict__ su,
                                             unsigned long long *__restrict__ ncount)
 {
@@ -128,6 +145,151 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
             const bool in = pin && gofs[k] >= 0;
             const double x = uin[in ? gofs[k] + sz * p : 0];
             v[k] = in ? x : 0.0;
+        }
+    };
+
+    // ---- prolongation (PRO): the coarse ring after the fine one.  This
+    // thread's share of a coarse plane (coarse offset inside the plane, -1:
+    // outside the coarse grid) and, for each of its plane elements, the
+    // ring offset of the coarse node below it and its parities (bit 2: the
+    // element is an interior node in x and y).
+    constexpr int CX = S::CX, CPL = S::CPL, CR = S::CR;
+    constexpr int KC = PRO ? (CPL + NT - 1) / NT : 1;
+    const int nch = n / 2, ccy = nch + 1, ccz = ccy * ccy;
+    const int cxa = (lx0 - 1) / 2, cya = (ly0 - 1) / 2;   // lx0, ly0 are odd
+    double *cr = su + S::NL;
+    int cgofs[KC], fco[KL], fpar[KL];
+    if (PRO) {
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int el = tid + k * NT;
+            const int cyy = el / CX, cxx = el - (el / CX) * CX;
+            const int X = cxa + cxx, Y = cya + cyy;
+            cgofs[k] = el < CPL && X >= 0 && X <= nch && Y >= 0 && Y <= nch ? X + ccy * Y : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const int el = tid + k * NT;
+            const int ly = el / LX, lx = el - (el / LX) * LX;
+            const int gx = lx0 + lx, gy = ly0 + ly;
+            const bool inxy = el < PL && gx >= 1 && gx <= n - 1 && gy >= 1 && gy <= n - 1;
+            fco[k] = inxy ? ((gy >> 1) - cya) * CX + ((gx >> 1) - cxa) : 0;
+            fpar[k] = inxy ? 4 | (gx & 1) | ((gy & 1) << 1) : 0;
+        }
+    }
+    const auto gcu = to_global(G.cu);
+    const auto gcw = to_global(G.cw);
+    // The loads land in a and b as they are; put_coarse masks the nodes
+    // outside the coarse grid (a select right after the load would make the
+    // step wait for every load in flight).
+    auto fetch_coarse = [&](int K, double *a, double *b) {
+        const bool kin = K >= 0 && K <= nch;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int q = kin && cgofs[k] >= 0 ? cgofs[k] + ccz * K : 0;
+            a[k] = gcu[q];
+            b[k] = gcw[q];
+        }
+    };
+    auto put_coarse = [&](int K, const double *a, const double *b) {
+        const bool kin = K >= 0 && K <= nch;
+        double *c = cr + (K & (CR - 1)) * CPL;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int el = tid + k * NT;
+            if (el < CPL)
+                c[el] = kin && cgofs[k] >= 0 ? a[k] - b[k] : 0.0;
+        }
+    };
+    // v += P e for the elements of plane p (PRO, interior planes), read
+    // straight from the coarse ring: the planes the prologue loads.  Element
+    // k's coarse nodes below it are (X, Y), (X + 1, Y), (X, Y + 1),
+    // (X + 1, Y + 1) of coarse plane p >> 1 and, for odd p, of the next; a
+    // node sums those its parities select (x odd: X + 1 too, y odd: Y + 1
+    // too) in the prolongation kernels' order -- coarse plane, row, column
+    // -- from d = 0.
+    auto correct_flat = [&](int p, double *v) {
+        if (!(PRO && p >= 1 && p <= n - 1))
+            return;
+        const int ok = p & 1;
+        const double *E0 = cr + ((p >> 1) & (CR - 1)) * CPL;
+        const double *E1 = cr + (((p >> 1) + 1) & (CR - 1)) * CPL;
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            if (!(fpar[k] & 4))
+                continue;
+            const int oi = fpar[k] & 1, oj = (fpar[k] >> 1) & 1;
+            const double wi = oi ? 0.5 : 1.0, wj = oj ? 0.5 : 1.0;
+            const double wk = ok ? 0.5 : 1.0;
+            const double w = wk * wj * wi;
+            double d = 0.0;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if (c == 1 && !ok)
+                    break;
+                const double *a = (c ? E1 : E0) + fco[k];
+                d += w * a[0];
+                if (oi)
+                    d += w * a[1];
+                if (oj) {
+                    d += w * a[CX];
+                    if (oi)
+                        d += w * a[CX + 1];
+                }
+            }
+            v[k] += d;
+        }
+    };
+    // The walk's planes from partial sums kept per element.  With
+    // B_K = 0 + (wj wi e) over the selected nodes of coarse plane K (in the
+    // order above), an even plane 2K is corrected by B_K, and an odd plane
+    // 2K + 1 by (B_K + the terms of plane K + 1) / 2: the weights are powers
+    // of two, so halving commutes with every rounding of the sum and both
+    // equal the prolongation kernels' sums bitwise.  Odd steps read coarse
+    // plane K = (s + 3) / 2 once per element for both B_K and the sum.
+    double Bp[KL];
+    auto bsum = [&](const double *a, int k, double start, double &b, double &sm) {
+        const int oi = fpar[k] & 1, oj = (fpar[k] >> 1) & 1;
+        const double wi = oi ? 0.5 : 1.0, wj = oj ? 0.5 : 1.0;
+        const double w2 = wj * wi;
+        const double t0 = a[0], t1 = a[1], t2 = a[CX], t3 = a[CX + 1];
+        b = 0.0;
+        sm = start;
+        b += w2 * t0;
+        sm += w2 * t0;
+        if (oi) {
+            b += w2 * t1;
+            sm += w2 * t1;
+        }
+        if (oj) {
+            b += w2 * t2;
+            sm += w2 * t2;
+            if (oi) {
+                b += w2 * t3;
+                sm += w2 * t3;
+            }
+        }
+    };
+    auto correct_step = [&](int s, double *v) {
+        const int p = s + 2;
+        const bool pin = p >= 1 && p <= n - 1;
+        if (s & 1) {
+            const double *E = cr + (((s + 3) >> 1) & (CR - 1)) * CPL;
+#pragma unroll
+            for (int k = 0; k < KL; ++k) {
+                if (!(fpar[k] & 4))
+                    continue;
+                double b, sm;
+                bsum(E + fco[k], k, Bp[k], b, sm);
+                if (pin)
+                    v[k] += 0.5 * sm;
+                Bp[k] = b;
+            }
+        } else if (pin) {
+#pragma unroll
+            for (int k = 0; k < KL; ++k)
+                if (fpar[k] & 4)
+                    v[k] += Bp[k];
         }
     };
     auto put_plane = [&](int p, const double *v) {
@@ -259,10 +421,34 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // step s - 2, so each step's loads have two steps to arrive.
     const int S0 = max(1, z0 - 3);
     const int S1 = min(n - 1, z1 - 1) + 6;
+    // Coarse planes (PRO): the even steps s >= sw0 write plane s / 2 + 2
+    // (loaded two steps earlier) and load the next one; the planes the
+    // prologue's fine planes and the first steps' fine planes read go into
+    // the ring here, before them.
+    const int sw0 = S0 + (S0 & 1);
+    double ca[KC], cb[KC];
+    if (PRO) {
+        for (int K = (S0 - 1) >> 1; K <= sw0 / 2 + 1; ++K) {
+            fetch_coarse(K, ca, cb);
+            put_coarse(K, ca, cb);
+        }
+        lds_barrier();
+        fetch_coarse(sw0 / 2 + 2, ca, cb);
+        // B of the coarse plane below the first step's even plane
+        const double *E = cr + (((S0 + 2) >> 1) & (CR - 1)) * CPL;
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            double sm;
+            Bp[k] = 0.0;
+            if (fpar[k] & 4)
+                bsum(E + fco[k], k, 0.0, Bp[k], sm);
+        }
+    }
     {
         double v[KL];
         for (int p = S0 - 1; p <= S0 + 1; ++p) {
             fetch_plane(p, v);
+            correct_flat(p, v);
             put_plane(p, v);
         }
     }
@@ -278,11 +464,17 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         store_plane(0);
 
     // one step: issue the loads of plane s+4 into pn and of the right-hand
-    // sides of step s+2 into fn, store plane s-7, update with fc, then write
-    // plane s+2 (loaded two steps earlier into pw) to LDS
+    // sides of step s+2 into fn, (PRO) correct plane s+2, store plane s-7,
+    // update with fc, then write plane s+2 (loaded two steps earlier into
+    // pw) to LDS
     auto step = [&](int s, double *pn, double *pw, double *fc, double *fn) {
         fetch_plane(s + 4, pn);
         fetch_f(s + 2, fn);
+        // the correction of plane s + 2 (its coarse planes are in the ring
+        // since earlier steps) ahead of the updates, whose work hides the
+        // latency of its reads
+        if (PRO)
+            correct_step(s, pw);
         const int q = s - 7;
         if (q >= z0 && q < z1) {
             store_plane(q);
@@ -295,6 +487,11 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
                 update(m, s, fc[m]);
         }
         put_plane(s + 2, pw);
+        if (PRO && !(s & 1)) {
+            // plane s / 2 + 2 into a slot this step's fine plane does not read
+            put_coarse(s / 2 + 2, ca, cb);
+            fetch_coarse(s / 2 + 3, ca, cb);
+        }
         lds_barrier();
     };
     for (int s = S0; s <= S1 + 1; s += 3) {
@@ -311,11 +508,11 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
 // Blocks are dispatched round-robin over the 8 XCDs; tile_of_block gives
 // each XCD a contiguous range of columns (x fastest, then y, then the z
 // chunk), so columns that share halos share an L2.
-template <int OP, int TX, int TY, int NT>
+template <int OP, int TX, int TY, int NT, bool PRO>
 __global__ __launch_bounds__(NT) void k_zsweep(const FsList *__restrict__ L,
                                                unsigned long long *__restrict__ ncount)
 {
-    __shared__ double su[ZsShape<TX, TY>::NL];
+    __shared__ double su[PRO ? ZsShape<TX, TY>::NLP : ZsShape<TX, TY>::NL];
     const int total = L->total;
     const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
     if (t >= total)
@@ -327,7 +524,7 @@ __global__ __launch_bounds__(NT) void k_zsweep(const FsList *__restrict__ L,
     const FsGrid G = L->g[g];
     if ((L->stopped >> G.slot) & 1ull)
         return;
-    zsweep_tile<OP, TX, TY, NT>(G, t - G.start, su, ncount);
+    zsweep_tile<OP, TX, TY, NT, PRO>(G, t - G.start, su, ncount);
 }
 
 template <int OP, int TX, int TY, int NT>
@@ -335,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_zsweep1(FsGrid G, unsigned long long *__
 {
     __shared__ double su[ZsShape<TX, TY>::NL];
     const int t = tile_of_block(int(blockIdx.x), int(gridDim.x));
-    zsweep_tile<OP, TX, TY, NT>(G, t, su, ncount);
+    zsweep_tile<OP, TX, TY, NT, false>(G, t, su, ncount);
 }
 
 } // namespace mafas

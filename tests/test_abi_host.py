@@ -80,7 +80,8 @@ def test_create_rejects_invalid_params_without_gpu():
                        ("restriction", 5), ("inner_cycles", 0), ("smoother", 3),
                        ("tile_config", 12), ("tile_config", -1), ("block_n", -2),
                        ("coarse_n", 33), ("max_blocks", 12), ("strip_rows", 5000),
-                       ("zsweep_n", -2), ("zsweep_n", 4096)):
+                       ("zsweep_n", -2), ("zsweep_n", 4096), ("fuse_prolong", 1),
+                       ("fuse_prolong", -2)):
         p = L.ma_params_default(16)
         setattr(p, field, val)
         with pytest.raises(L.MAError) as ei:

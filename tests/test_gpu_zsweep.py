@@ -50,3 +50,57 @@ def test_zsweep_full_size_bitwise_vs_colour(n):
         torch.cuda.synchronize()
         assert torch.equal(uz, uc), cfg
         del uz
+
+
+def _solve(n, kind, seed, **kw):
+    s = solver(n, **kw)
+    u0, f = P.make_device(kind, n, seed)
+    u = u0.clone()
+    rep = s.solve(u, f, tol=1e-9)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("n,kind,kw", [
+    (256, "exp_cos", {}),                                   # automatic: finest level only
+    (128, "quadratic", {"smoother": "fused", "tile_config": 8}),
+    (96, "exp_cos", {"smoother": "fused", "tile_config": 9}),
+    (128, "exp_cos", {"smoother": "fused", "tile_config": 10}),
+    (64, "exp_cos", {"smoother": "fused", "tile_config": 11}),
+])
+def test_fused_prolongation_solve_bitwise(n, kind, kw):
+    """Solves whose first post-smoothing z-stream sweep also applies the
+    coarse-grid correction (no separate prolongation pass) equal, bitwise
+    and in cycle count, the same solves with the separate pass and with
+    colour phases everywhere."""
+    note("fused prolongation solve", n, kind, kw)
+    uf, rf = _solve(n, kind, 8100 + n, **kw)
+    us, rs = _solve(n, kind, 8100 + n, fuse_prolong=-1, **kw)
+    uc, rc = _solve(n, kind, 8100 + n, smoother="color")
+    assert rf["cycles"] == rs["cycles"] == rc["cycles"]
+    assert np.array_equal(uf, us)
+    assert np.array_equal(uf, uc)
+
+
+def test_fused_prolongation_batch_bitwise():
+    """A batch of different sizes, z-stream sweeps on every multi-block
+    level: each solve's result is that of colour phases."""
+    from paper_1411_7018_amd.batch import solve_batch
+    specs = [("quadratic", 128, 1), ("exp_cos", 64, 2), ("example4", 96, 3), ("exp_cos", 48, 4)]
+    note("fused prolongation batch")
+    res = {}
+    for mode in ("color", "zs"):
+        kw = {"smoother": "color"} if mode == "color" else {"smoother": "fused", "tile_config": 8}
+        solvers, us, fs = [], [], []
+        for kind, n, seed in specs:
+            u0, f = P.make_device(kind, n, seed)
+            solvers.append(solver(n, **kw))
+            us.append(u0)
+            fs.append(f)
+        st, reps = solve_batch(solvers, us, fs, tol=1e-9)
+        assert st == 0
+        torch.cuda.synchronize()
+        res[mode] = ([u.cpu().numpy() for u in us], [r["cycles"] for r in reps])
+    assert res["zs"][1] == res["color"][1]
+    for a, c in zip(res["zs"][0], res["color"][0]):
+        assert np.array_equal(a, c)
