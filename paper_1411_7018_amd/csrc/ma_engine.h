@@ -26,8 +26,8 @@ constexpr int kNormRing = 4;
 // z-stream sweeps (ma_zsweep.h): first shape index among the block-sweep
 // configurations, and the smallest level that takes them when zsweep_n = 0
 constexpr int kZsFirstConfig = 7;
-constexpr int kZsweepAuto = 256;      // Monge-Ampere sweeps
-constexpr int kZsweepAutoLap = 256;   // linear sweeps of the Poisson guess
+constexpr int kZsweepAuto = 192;      // Monge-Ampere sweeps
+constexpr int kZsweepAutoLap = 192;   // linear sweeps of the Poisson guess
 constexpr int kDefaultMaxBlocks = 16384;
 constexpr int kTailThreads = 512;      // threads of the coarse-level kernel
 constexpr int kMaxTail = 6;            // levels per solve inside that kernel

@@ -1561,9 +1561,12 @@ bool Engine::block_level(int n, Mode mode) const
 // Automatic choice (zsweep_n = 0), from whole-solve timings on MI355X: the
 // z-stream sweep moves each node once per sweep but recomputes ~23% of the
 // updates and waits on its barriers, and a grid needs enough 32 x 26
-// columns to give every compute unit a chunk of planes; it pays from
-// n = 256 (Monge-Ampere sweeps 169 against 201 us at 257^3 and 564 against
-// 801 us at 385^3, Poisson sweeps alike; at 129^3 51 against 36 us).
+// columns to give every compute unit a chunk of planes; with the
+// prolongation folded into the first post-smoothing sweep it pays from
+// n = 192 (385^3 solve 68.8 -> 66.7 ms with level 192 as z-stream sweeps;
+// Monge-Ampere sweeps 169 against 201 us at 257^3 and 564 against 801 us at
+// 385^3, Poisson sweeps alike) but not at n = 128 (257^3 solve 22.1 against
+// 23.0 ms, 129^3 6.0 against 7.1 ms).
 bool Engine::zs_level(int n, Mode mode) const
 {
     if (order_ != MA_COLOR4 || smoother_ != MA_SMOOTHER_AUTO)
