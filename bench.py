@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size), keyed by (workload, kernel); valid only for the kernel as it
 # was profiled.
-TRAFFIC = {("served", "k_zsweep"): 1.745e9}   # profiles/k_zsweep_expcos385.md
+TRAFFIC = {("served", "k_zsweep"): 1.786e9}   # profiles/k_zsweep_expcos385.md
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
@@ -562,8 +562,10 @@ def served_roofline():
     tp = time.perf_counter() - t0
     r = roofline(reps, TRAFFIC.get(("served", "k_zsweep")))
     r["kernel"] = ("finest-level smoother of a 385^3 request: z-stream sweeps (k_zsweep, all "
-                   "four colour phases per launch; Monge-Ampere and Poisson sweeps), 24 B per "
-                   "interior node per sweep")
+                   "four colour phases per launch; Monge-Ampere and Poisson sweeps; the first "
+                   "post-smoothing sweep of a cycle also applies the coarse-grid correction), "
+                   "24 B per interior node per sweep plus 16 B per coarse node for the "
+                   "prolonging sweeps")
     r.update(instrumented(reps, tp, 1))
     r["pass"] = ("two instrumented 385^3 exp-cos solves after the served runs, HIP events on "
                  "the engine stream around every group of finest-level sweep launches")
