@@ -190,6 +190,26 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes": count * 8, "copies": 20}), flush=True)
 
 
+def diff_vs_fp64(ns, us_init, fs, us_done, tol, init="poisson"):
+    """Max-norm difference of mixed-precision results from the same problems
+    solved by the FP64 path (outside the timed region): the agreement the
+    mixed form reaches at the benchmark's stopping tolerance."""
+    import torch
+
+    from paper_1411_7018_amd import Solver
+
+    worst = 0.0
+    for n, u0, f, u in zip(ns, us_init, fs, us_done):
+        s = Solver(n, precision="fp64")
+        w = u0.clone()
+        s.solve(w, f, tol=tol, init=init)
+        torch.cuda.synchronize()
+        worst = max(worst, float((w - u).abs().max()))
+        s.close()
+        del w
+    return worst
+
+
 def retune_like(solvers, choice):
     """Give the instrumented solvers the launch shape the timed ones use."""
     if choice is not None:
@@ -256,6 +276,7 @@ def run_single(args, precision):
     elapsed = time.perf_counter() - t0
     last = reps[-1]
     err = float(np.abs(u.cpu().numpy() - prob.u_exact).max())
+    dmix = (diff_vs_fp64([n], [u_init], [f], [u], tol, init) if precision == "mixed" else None)
     step(sp)
     torch.cuda.synchronize()
     preps = []
@@ -275,6 +296,7 @@ def run_single(args, precision):
     out.update({"updates_per_s": sum(r["point_updates"] for r in reps) / elapsed,
                 "cycles": last["cycles"], "init_cycles": last["init_cycles"],
                 "rel_res": last["rel_res"], "max_err_vs_exact": err,
+                **({"max_abs_diff_vs_fp64": dmix} if dmix is not None else {}),
                 "roofline": dict(roofline(preps, TRAFFIC.get((args.workload, precision))),
                                  **instrumented(preps, tp, 1))})
     if not args.no_cpu_baseline:
@@ -399,6 +421,8 @@ def run_batch(args, precision):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     nsol = len(specs)
+    dmix = (diff_vs_fp64([n for _, n, _ in specs], us0, fs, us, 1e-8)
+            if precision == "mixed" else None)
     step(psolvers)
     torch.cuda.synchronize()
     preps = []
@@ -420,6 +444,7 @@ def run_batch(args, precision):
                 / elapsed,
                 "max_cycles": max(r["cycles"] for r in allreps[-1]),
                 "max_rel_res": max(r["rel_res"] for r in allreps[-1]),
+                **({"max_abs_diff_vs_fp64": dmix} if dmix is not None else {}),
                 "roofline": dict(roofline([reps[0] for reps in preps]),
                                  **instrumented(preps, tp, nsol))})
     return out
