@@ -63,6 +63,7 @@ def _solve(n, kind, seed, **kw):
 
 @pytest.mark.parametrize("n,kind,kw", [
     (256, "exp_cos", {}),                                   # automatic: finest level only
+    (224, "exp_cos", {}),                                   # automatic, ragged columns and chunks
     (128, "quadratic", {"smoother": "fused", "tile_config": 8}),
     (96, "exp_cos", {"smoother": "fused", "tile_config": 9}),
     (128, "exp_cos", {"smoother": "fused", "tile_config": 10}),
