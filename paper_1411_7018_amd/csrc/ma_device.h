@@ -197,6 +197,12 @@ __device__ __noinline__ double gershgorin_start(Hess g, double F)
 // perturbs the iteration, not its limit.  Stop when the step is below 1e-9 of
 // the eigenvalue scale AND below 1e-3 of the previous step: in the quadratic
 // phase the error after such a step is O(step^2 / scale), i.e. at round-off.
+// The test starts after the second step: nearly every node needs two steps
+// (one to reach the root, one to show it has), a second step from a root
+// moves it by round-off at most, and in a wavefront the two steps then run
+// as one branch-free sequence instead of two passes through the loop's
+// exit logic.  A node whose first step is already below 1e-9 of the scale
+// is settled after the second, as it would have been after the first.
 // Near a double smallest eigenvalue with tiny F the iteration converges only
 // linearly (steps halve), and a small step says nothing about the remaining
 // error; the ratio test keeps it going until the root separates, and a node
@@ -220,21 +226,32 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         sig = gershgorin_start(g, F);
     const double c0 = I3 - F;
     const double thr = 1e-9 * (fabs(I1) + fabs(sig));
-    double dprev = INFINITY;
-    bool settled = false;
-    for (int it = 0; it < 64; ++it) {
+    // one Newton step; returns |step|
+    auto newton = [&]() {
         const double q = ((I1 - sig) * sig - I2) * sig + c0;
         const double dq = (2.0 * I1 - 3.0 * sig) * sig - I2;
         double r = __builtin_amdgcn_rcp(dq);
         r = fma(r, fma(-dq, r, 1.0), r);
         const double d = q * r;
         sig -= d;
-        const double ad = fabs(d);
-        if (!(ad > thr) && !(ad > 1e-3 * dprev)) {
-            settled = true;
-            break;
-        }
+        return fabs(d);
+    };
+    double dprev = newton();
+    double ad = newton();
+    // a first step already below the threshold settles the node as it
+    // would have alone (the second is then round-off, as large as the first
+    // may be, and the ratio test says nothing)
+    bool settled = !(ad > thr) && (!(ad > 1e-3 * dprev) || !(dprev > thr));
+    if (!settled) {
         dprev = ad;
+        for (int it = 2; it < 64; ++it) {
+            ad = newton();
+            if (!(ad > thr) && !(ad > 1e-3 * dprev)) {
+                settled = true;
+                break;
+            }
+            dprev = ad;
+        }
     }
     if (!settled || !isfinite(sig)) {
         nonconvex = true;
