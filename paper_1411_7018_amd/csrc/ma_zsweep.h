@@ -95,8 +95,35 @@ __host__ __device__ inline int zs_chunk(int n, int chunks)
     return (n - 1 + chunks - 1) / chunks;
 }
 
-// Column `tile` of grid G by a workgroup of NT threads; su: LDS.  Global
-// offsets are 32-bit: grids up to n = 1289.
+// Raw buffer accesses for the walk's global loads and stores.  A buffer
+// resource carries a base address and a size in bytes; a byte offset at or
+// beyond the size reads 0 and drops a write.  Each plane gets a resource
+// whose base is a scalar (the plane's first node), each thread keeps its
+// byte offsets inside a plane in registers, and a node outside the grid
+// carries kZsOob: no address arithmetic, select or branch per access.
+constexpr unsigned kZsOob = 0x80000000u;
+constexpr int kZsRsrcFlags = 0x00020000;   // buffer resource word 3 (gfx9)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t zs_rsrc(const double *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), (short)0, int(bytes),
+                                             kZsRsrcFlags);
+}
+
+__device__ __forceinline__ double zs_load(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
+}
+
+__device__ __forceinline__ void zs_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v)
+{
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(off), 0, 0);
+}
+
+// Column `tile` of grid G by a workgroup of NT threads; su: LDS.  Byte
+// offsets inside a plane and plane bases are 32- and 64-bit: grids up to
+// n = 1289 (element offsets of the coarse loads are 32-bit).
 template <int OP, int TX, int TY, int NT, bool PRO>
 __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *__restrict__ su,
                                             unsigned long long *__restrict__ ncount)
@@ -121,31 +148,29 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     const int x1 = min(x0 + TX, n), y1 = min(y0 + TY, n), z1 = min(z0 + zc, n);
     const int lx0 = x0 - H, ly0 = y0 - H;
     const int sy = n + 1, sz = sy * sy;
-    const auto uin = to_global(G.uin);
-    const auto uout = to_global(G.uout);
-    const auto F = to_global(G.F);
 
     // ---- this thread's share of a plane load: global offset inside the
     // plane (-1: outside the grid, LDS gets 0) and LDS offset inside a slot
-    int gofs[KL], lofs[KL];
+    unsigned gofs[KL];
+    int lofs[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
         const int el = tid + k * NT;
         const int ly = el / LX, lx = el - (el / LX) * LX;
         const int gx = lx0 + lx, gy = ly0 + ly;
         const bool in = el < PL && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
-        gofs[k] = in ? gx + sy * gy : -1;
+        gofs[k] = in ? unsigned(gx + sy * gy) * 8u : kZsOob;
         lofs[k] = el < PL ? ly * LX + (lx & 1) * HW + (lx >> 1) : -1;
     }
+    const unsigned plane_bytes = unsigned(sz) * 8u;
     auto slot = [&](int p) { return ((p + 2 * R) % R) * PL; };   // p >= -2R
+    // planes outside the grid read 0 through an empty resource
     auto fetch_plane = [&](int p, double *v) {
         const bool pin = p >= 0 && p <= n;
+        const auto r = zs_rsrc(G.uin + (pin ? size_t(sz) * p : 0), pin ? plane_bytes : 0u);
 #pragma unroll
-        for (int k = 0; k < KL; ++k) {
-            const bool in = pin && gofs[k] >= 0;
-            const double x = uin[in ? gofs[k] + sz * p : 0];
-            v[k] = in ? x : 0.0;
-        }
+        for (int k = 0; k < KL; ++k)
+            v[k] = zs_load(r, gofs[k]);
     };
 
     // ---- prolongation (PRO): the coarse ring after the fine one.  This
@@ -304,7 +329,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // (-1: none), the planes its colour covers, and for each parity of the
     // step the node's offsets inside a plane (LDS and global), whether it
     // lies in the grid interior and whether this column owns it.
-    int ic[MI], plo[MI], phi[MI], lio[MI][2], gio[MI][2];
+    int ic[MI], plo[MI], phi[MI], lio[MI][2];
+    unsigned gio[MI][2];
     bool okxy[MI][2], own[MI][2];
 #pragma unroll
     for (int m = 0; m < MI; ++m) {
@@ -335,7 +361,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
             const int j = ya + ((ya + c1 + sp + c0) & 1) + 2 * r;
             const int lx = i - lx0;
             lio[m][sp] = (j - ly0) * LX + (lx & 1) * HW + (lx >> 1);
-            gio[m][sp] = i + sy * j;
+            // byte offset of the node in plane P = s - 2c from plane s - 6
+            gio[m][sp] = unsigned(i + sy * j + (6 - 2 * cc) * sz) * 8u;
             okxy[m][sp] = c >= 0 && i >= max(1, xa) && i <= min(n - 1, x1 - 1 + e) &&
                           j >= max(1, ya) && j <= min(n - 1, y1 - 1 + e);
             own[m][sp] = i >= x0 && i < x1 && j >= y0 && j < y1;
@@ -345,14 +372,18 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     auto active = [&](int m, int sp, int P) {
         return okxy[m][sp] && P >= plo[m] && P <= phi[m];
     };
+    // right-hand sides of the items at step s: one resource based at plane
+    // s - 6 (it may start below the grid; every offset read lands on the
+    // item's own plane P = s - 2c >= 1), inactive items read 0
     auto fetch_f = [&](int s, double *f) {
         const int sp = s & 1;
+        const auto r = zs_rsrc(reinterpret_cast<const double *>(
+                                   reinterpret_cast<uintptr_t>(G.F) + (long(s) - 6) * long(plane_bytes)),
+                               7u * plane_bytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             const int P = s - 2 * ic[m];
-            const bool ok = active(m, sp, P);
-            const double x = F[ok ? gio[m][sp] + sz * P : 0];
-            f[m] = x;
+            f[m] = zs_load(r, active(m, sp, P) ? gio[m][sp] : kZsOob);
         }
     };
 
@@ -401,18 +432,26 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // ---- write plane q (owned nodes and the Dirichlet layer beside them)
     const int xs0 = x0 == 1 ? 0 : x0, xs1 = x1 == n ? n + 1 : x1;
     const int ys0 = y0 == 1 ? 0 : y0, ys1 = y1 == n ? n + 1 : y1;
+    // this thread's share of a stored plane: byte offset in the grid plane
+    // (kZsOob: none) and LDS offset in a slot
+    unsigned sofs[KS];
+    int sl[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int el = tid + k * NT;
+        const int bb = el / SX, a = el - (el / SX) * SX;
+        const int gx = xs0 + a, gy = ys0 + bb;
+        const bool in = el < SX * SY && gx < xs1 && gy < ys1;
+        const int lx = gx - lx0;
+        sofs[k] = in ? unsigned(gx + sy * gy) * 8u : kZsOob;
+        sl[k] = in ? (gy - ly0) * LX + (lx & 1) * HW + (lx >> 1) : 0;
+    }
     auto store_plane = [&](int q) {
         const double *b = su + slot(q);
+        const auto r = zs_rsrc(G.uout + size_t(sz) * q, plane_bytes);
 #pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            const int el = tid + k * NT;
-            const int bb = el / SX, a = el - (el / SX) * SX;
-            const int gx = xs0 + a, gy = ys0 + bb;
-            if (el < SX * SY && gx < xs1 && gy < ys1) {
-                const int lx = gx - lx0;
-                uout[gx + sy * gy + sz * q] = b[(gy - ly0) * LX + (lx & 1) * HW + (lx >> 1)];
-            }
-        }
+        for (int k = 0; k < KS; ++k)
+            zs_store(r, sofs[k], b[sl[k]]);
     };
 
     // ---- the walk.  Steps S0..S1 update; plane q is stored at step q + 7.
