@@ -25,6 +25,32 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(void *p)
     return (__attribute__((address_space(1))) T *)(p);
 }
 
+// Raw buffer accesses.  A buffer resource carries a base address and a size
+// in bytes; a byte offset at or beyond the size reads 0 and drops a write.
+// Kernels that walk a grid plane by plane build one resource per plane,
+// whose base (the plane's first node) is a scalar, keep each thread's byte
+// offsets inside a plane in registers, and give a node outside the grid the
+// offset kBufOob: no 64-bit address arithmetic, select or branch per access.
+constexpr unsigned kBufOob = 0x80000000u;
+constexpr int kBufRsrcFlags = 0x00020000;   // buffer resource word 3 (gfx9)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), (short)0, int(bytes),
+                                             kBufRsrcFlags);
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
+}
+
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v)
+{
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(off), 0, 0);
+}
+
 struct Hess {
     double xx, yy, zz, xy, xz, yz;
 };

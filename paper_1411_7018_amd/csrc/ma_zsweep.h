@@ -95,35 +95,10 @@ __host__ __device__ inline int zs_chunk(int n, int chunks)
     return (n - 1 + chunks - 1) / chunks;
 }
 
-// Raw buffer accesses for the walk's global loads and stores.  A buffer
-// resource carries a base address and a size in bytes; a byte offset at or
-// beyond the size reads 0 and drops a write.  Each plane gets a resource
-// whose base is a scalar (the plane's first node), each thread keeps its
-// byte offsets inside a plane in registers, and a node outside the grid
-// carries kZsOob: no address arithmetic, select or branch per access.
-constexpr unsigned kZsOob = 0x80000000u;
-constexpr int kZsRsrcFlags = 0x00020000;   // buffer resource word 3 (gfx9)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t zs_rsrc(const double *base, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(base), (short)0, int(bytes),
-                                             kZsRsrcFlags);
-}
-
-__device__ __forceinline__ double zs_load(__amdgpu_buffer_rsrc_t r, unsigned off)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
-}
-
-__device__ __forceinline__ void zs_store(__amdgpu_buffer_rsrc_t r, unsigned off, double v)
-{
-    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(off), 0, 0);
-}
-
-// Column `tile` of grid G by a workgroup of NT threads; su: LDS.  Byte
-// offsets inside a plane and plane bases are 32- and 64-bit: grids up to
-// n = 1289 (element offsets of the coarse loads are 32-bit).
+// Column `tile` of grid G by a workgroup of NT threads; su: LDS.  The
+// plane loads and stores go through raw buffer accesses (buf_rsrc), one
+// resource per plane, byte offsets inside a plane in registers.  Grids up
+// to n = 1289 (element offsets of the coarse loads are 32-bit).
 template <int OP, int TX, int TY, int NT, bool PRO>
 __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *__restrict__ su,
                                             unsigned long long *__restrict__ ncount)
@@ -159,7 +134,7 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         const int ly = el / LX, lx = el - (el / LX) * LX;
         const int gx = lx0 + lx, gy = ly0 + ly;
         const bool in = el < PL && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
-        gofs[k] = in ? unsigned(gx + sy * gy) * 8u : kZsOob;
+        gofs[k] = in ? unsigned(gx + sy * gy) * 8u : kBufOob;
         lofs[k] = el < PL ? ly * LX + (lx & 1) * HW + (lx >> 1) : -1;
     }
     const unsigned plane_bytes = unsigned(sz) * 8u;
@@ -167,10 +142,10 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // planes outside the grid read 0 through an empty resource
     auto fetch_plane = [&](int p, double *v) {
         const bool pin = p >= 0 && p <= n;
-        const auto r = zs_rsrc(G.uin + (pin ? size_t(sz) * p : 0), pin ? plane_bytes : 0u);
+        const auto r = buf_rsrc(G.uin + (pin ? size_t(sz) * p : 0), pin ? plane_bytes : 0u);
 #pragma unroll
         for (int k = 0; k < KL; ++k)
-            v[k] = zs_load(r, gofs[k]);
+            v[k] = buf_load(r, gofs[k]);
     };
 
     // ---- prolongation (PRO): the coarse ring after the fine one.  This
@@ -368,6 +343,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
             own[m][sp] = i >= x0 && i < x1 && j >= y0 && j < y1;
         }
     }
+    // nonconvex updates of owned nodes (added to ncount after the walk)
+    unsigned nown = 0;
     // item m has a node at step s (sp = s & 1, P = s - 2c)
     auto active = [&](int m, int sp, int P) {
         return okxy[m][sp] && P >= plo[m] && P <= phi[m];
@@ -377,13 +354,13 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // item's own plane P = s - 2c >= 1), inactive items read 0
     auto fetch_f = [&](int s, double *f) {
         const int sp = s & 1;
-        const auto r = zs_rsrc(reinterpret_cast<const double *>(
+        const auto r = buf_rsrc(reinterpret_cast<const double *>(
                                    reinterpret_cast<uintptr_t>(G.F) + (long(s) - 6) * long(plane_bytes)),
                                7u * plane_bytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
             const int P = s - 2 * ic[m];
-            f[m] = zs_load(r, active(m, sp, P) ? gio[m][sp] : kZsOob);
+            f[m] = buf_load(r, active(m, sp, P) ? gio[m][sp] : kBufOob);
         }
     };
 
@@ -416,8 +393,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
                 bool nc = false;
                 C[0] = ma_point_update(h, C[0], f, G.hk, nc);
                 // recomputed halo nodes are counted by their own column / chunk
-                if (nc && ncount && own[m][sp] && P >= z0 && P < z1)
-                    atomicAdd(ncount + G.slot, 1ull);
+                if (nc)
+                    nown += own[m][sp] && P >= z0 && P < z1;
             } else {
                 const double lap = laplacian3(D, C, U, xp, xm, LX, G.s);
                 C[0] = lap_point_update(lap, C[0], f, G.hk);
@@ -433,7 +410,7 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     const int xs0 = x0 == 1 ? 0 : x0, xs1 = x1 == n ? n + 1 : x1;
     const int ys0 = y0 == 1 ? 0 : y0, ys1 = y1 == n ? n + 1 : y1;
     // this thread's share of a stored plane: byte offset in the grid plane
-    // (kZsOob: none) and LDS offset in a slot
+    // (kBufOob: none) and LDS offset in a slot
     unsigned sofs[KS];
     int sl[KS];
 #pragma unroll
@@ -443,15 +420,15 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         const int gx = xs0 + a, gy = ys0 + bb;
         const bool in = el < SX * SY && gx < xs1 && gy < ys1;
         const int lx = gx - lx0;
-        sofs[k] = in ? unsigned(gx + sy * gy) * 8u : kZsOob;
+        sofs[k] = in ? unsigned(gx + sy * gy) * 8u : kBufOob;
         sl[k] = in ? (gy - ly0) * LX + (lx & 1) * HW + (lx >> 1) : 0;
     }
     auto store_plane = [&](int q) {
         const double *b = su + slot(q);
-        const auto r = zs_rsrc(G.uout + size_t(sz) * q, plane_bytes);
+        const auto r = buf_rsrc(G.uout + size_t(sz) * q, plane_bytes);
 #pragma unroll
         for (int k = 0; k < KS; ++k)
-            zs_store(r, sofs[k], b[sl[k]]);
+            buf_store(r, sofs[k], b[sl[k]]);
     };
 
     // ---- the walk.  Steps S0..S1 update; plane q is stored at step q + 7.
@@ -542,6 +519,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
             break;
         step(s + 2, p2, p0, f2, f1);
     }
+    if (OP == OP_MA && ncount && nown)
+        atomicAdd(ncount + G.slot, (unsigned long long)nown);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; tile_of_block gives
