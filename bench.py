@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size), keyed by (workload, kernel); valid only for the kernel as it
 # was profiled.
-TRAFFIC = {("served", "k_zsweep"): 1.786e9}   # profiles/k_zsweep_expcos385.md
+TRAFFIC = {("served", "k_zsweep"): 1.788e9}   # profiles/k_zsweep_expcos385.md
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
@@ -108,7 +108,10 @@ def roofline(reps, traffic=None):
     ach = by / sec / 1e9 if sec > 0 else 0.0
     out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
-           "kernel": "k_batched sweep, finest level (24 B per interior node per sweep)",
+           "kernel": ("finest-level smoother launches: z-stream sweeps (k_zsweep) on levels at "
+                      "or above the z-stream threshold, else colour phases (k_batched) or block "
+                      "sweeps (k_bsweep); 24 B per interior node per sweep, plus 16 B per "
+                      "coarse node for z-stream sweeps that also prolong"),
            "avg_launch_us": 1e6 * sec / max(la, 1), "launches": la,
            "alg_bytes_per_launch": by / max(la, 1)}
     if traffic is not None:
