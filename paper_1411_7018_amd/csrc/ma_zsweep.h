@@ -292,8 +292,9 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
                     v[k] += Bp[k];
         }
     };
-    auto put_plane = [&](int p, const double *v) {
-        double *b = su + slot(p);
+    // plane elements into ring slot offset so (a multiple of PL)
+    auto put_plane = [&](int so, const double *v) {
+        double *b = su + so;
 #pragma unroll
         for (int k = 0; k < KL; ++k)
             if (lofs[k] >= 0)
@@ -367,16 +368,15 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // ---- the update of item m at step s, right-hand side f.  The x
     // parity of the node is uniform across the wavefront, so the branch on
     // it is too, and each side reads its neighbours at constant offsets.
-    auto update = [&](int m, int s, double f) {
+    auto update = [&](int m, int s, int rs, double f) {
         const int sp = s & 1;
         const int c = ic[m];
         const int P = s - 2 * c;
         if (!active(m, sp, P))
             return;
         const int io = lio[m][sp];
-        // ring slots of planes P, P - 1, P + 1 from the step's slot (s mod R,
-        // uniform): P = s - 2c with 0 <= 2c <= 6 wraps at most once
-        const int rs = s % R;
+        // ring slots of planes P, P - 1, P + 1 from the step's slot rs =
+        // s mod R: P = s - 2c with 0 <= 2c <= 6 wraps at most once
         int b = rs - 2 * c;
         b += b < 0 ? R : 0;
         const int bm = b == 0 ? R - 1 : b - 1;
@@ -423,8 +423,8 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         sofs[k] = in ? unsigned(gx + sy * gy) * 8u : kBufOob;
         sl[k] = in ? (gy - ly0) * LX + (lx & 1) * HW + (lx >> 1) : 0;
     }
-    auto store_plane = [&](int q) {
-        const double *b = su + slot(q);
+    auto store_plane = [&](int q, int so) {
+        const double *b = su + so;
         const auto r = buf_rsrc(G.uout + size_t(sz) * q, plane_bytes);
 #pragma unroll
         for (int k = 0; k < KS; ++k)
@@ -465,7 +465,7 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         for (int p = S0 - 1; p <= S0 + 1; ++p) {
             fetch_plane(p, v);
             correct_flat(p, v);
-            put_plane(p, v);
+            put_plane(slot(p), v);
         }
     }
     double p0[KL], p1[KL], p2[KL];   // plane prefetch buffers (rotate by step)
@@ -477,7 +477,7 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     lds_barrier();
     // the Dirichlet planes travel with the chunk next to them
     if (z0 == 1)
-        store_plane(0);
+        store_plane(0, slot(0));
 
     // one step: issue the loads of plane s+4 into pn and of the right-hand
     // sides of step s+2 into fn, (PRO) correct plane s+2, store plane s-7,
@@ -491,18 +491,26 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         // latency of its reads
         if (PRO)
             correct_step(s, pw);
+        // ring slot offsets of planes s + d from s mod R (uniform)
+        const int rs = s % R;
+        auto rslot = [&](int d) {
+            int x = rs + d;
+            x += x < 0 ? R : 0;
+            x -= x >= R ? R : 0;
+            return x * PL;
+        };
         const int q = s - 7;
         if (q >= z0 && q < z1) {
-            store_plane(q);
+            store_plane(q, rslot(-7));
             if (q == n - 1)
-                store_plane(n);
+                store_plane(n, rslot(-6));
         }
         if (s <= S1) {
 #pragma unroll
             for (int m = 0; m < MI; ++m)
-                update(m, s, fc[m]);
+                update(m, s, rs, fc[m]);
         }
-        put_plane(s + 2, pw);
+        put_plane(rslot(2), pw);
         if (PRO && !(s & 1)) {
             // plane s / 2 + 2 into a slot this step's fine plane does not read
             put_coarse(s / 2 + 2, ca, cb);
