@@ -243,16 +243,10 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
     const double I1 = g.xx + g.yy + g.zz;
     const double I2 = mab + (g.xx * g.zz - g.xz * g.xz) + (g.yy * g.zz - g.yz * g.yz);
     const double I3 = det3(g);
-    if (!(F > 0.0)) {
-        nonconvex = true;
-        return smallest_root_general(g, F);
-    }
-    double sig = 0.0;
-    if (!(g.xx > 0.0 && mab > 0.0 && I3 > 0.0))
-        sig = gershgorin_start(g, F);
     const double c0 = I3 - F;
-    const double thr = 1e-9 * (fabs(I1) + fabs(sig));
+    const bool spd = g.xx > 0.0 && mab > 0.0 && I3 > 0.0;
     // one Newton step; returns |step|
+    double sig = 0.0;
     auto newton = [&]() {
         const double q = ((I1 - sig) * sig - I2) * sig + c0;
         const double dq = (2.0 * I1 - 3.0 * sig) * sig - I2;
@@ -262,26 +256,45 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
         sig -= d;
         return fabs(d);
     };
-    double dprev = newton();
-    double ad = newton();
     // a first step already below the threshold settles the node as it
     // would have alone (the second is then round-off, as large as the first
     // may be, and the ratio test says nothing)
-    bool settled = !(ad > thr) && (!(ad > 1e-3 * dprev) || !(dprev > thr));
-    if (!settled) {
-        dprev = ad;
-        for (int it = 2; it < 64; ++it) {
-            ad = newton();
-            if (!(ad > thr) && !(ad > 1e-3 * dprev)) {
-                settled = true;
-                break;
+    auto test = [](double ad, double dprev, double thr) {
+        return !(ad > thr) && (!(ad > 1e-3 * dprev) || !(dprev > thr));
+    };
+    // Every lane takes the two steps from the SPD start sig = 0; one branch
+    // then sends the rest (a non-SPD Hessian, no settling yet, a non-finite
+    // iterate, F <= 0) down the full rule, which redoes the start where it
+    // differs.  A wavefront whose lanes all settle takes no other branch.
+    double thr = 1e-9 * (fabs(I1) + fabs(sig));
+    double dprev = newton();
+    double ad = newton();
+    bool settled = test(ad, dprev, thr);
+    if (!(F > 0.0 && spd && settled && isfinite(sig))) {
+        if (F > 0.0) {
+            if (!spd) {
+                sig = gershgorin_start(g, F);
+                thr = 1e-9 * (fabs(I1) + fabs(sig));
+                dprev = newton();
+                ad = newton();
+                settled = test(ad, dprev, thr);
             }
-            dprev = ad;
+            if (!settled) {
+                dprev = ad;
+                for (int it = 2; it < 64; ++it) {
+                    ad = newton();
+                    if (!(ad > thr) && !(ad > 1e-3 * dprev)) {
+                        settled = true;
+                        break;
+                    }
+                    dprev = ad;
+                }
+            }
         }
-    }
-    if (!settled || !isfinite(sig)) {
-        nonconvex = true;
-        return smallest_root_general(g, F);
+        if (!(F > 0.0) || !settled || !isfinite(sig)) {
+            nonconvex = true;
+            sig = smallest_root_general(g, F);
+        }
     }
     return sig;
 }
