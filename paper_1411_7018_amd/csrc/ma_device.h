@@ -259,8 +259,10 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
     // a first step already below the threshold settles the node as it
     // would have alone (the second is then round-off, as large as the first
     // may be, and the ratio test says nothing)
+    // (bitwise operators: all three comparisons are cheap, and a
+    // short-circuit would cost a divergent branch)
     auto test = [](double ad, double dprev, double thr) {
-        return !(ad > thr) && (!(ad > 1e-3 * dprev) || !(dprev > thr));
+        return bool(!(ad > thr) & (!(ad > 1e-3 * dprev) | !(dprev > thr)));
     };
     // Every lane takes the two steps from the SPD start sig = 0; one branch
     // then sends the rest (a non-SPD Hessian, no settling yet, a non-finite
@@ -270,7 +272,7 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
     double dprev = newton();
     double ad = newton();
     bool settled = test(ad, dprev, thr);
-    if (!(F > 0.0 && spd && settled && isfinite(sig))) {
+    if (!((F > 0.0) & spd & settled & bool(isfinite(sig)))) {
         if (F > 0.0) {
             if (!spd) {
                 sig = gershgorin_start(g, F);

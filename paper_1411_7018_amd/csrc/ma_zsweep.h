@@ -400,7 +400,15 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
                 C[0] = lap_point_update(lap, C[0], f, G.hk);
             }
         };
-        if (((c >> 1) + sp - lx0) & 1)
+        // colours 0 and 1 (2 and 3) share wavefronts and c >> 1, so the
+        // parity is the same on every active lane.  For the Monge-Ampere
+        // update it is read from the first active lane, which makes the
+        // branch a scalar branch instead of two exec-masked paths; the short
+        // Poisson update runs faster without the read.
+        int odd = ((c >> 1) + sp - lx0) & 1;
+        if (OP == OP_MA)
+            odd = __builtin_amdgcn_readfirstlane(odd);
+        if (odd)
             apply(std::integral_constant<int, 1>{});
         else
             apply(std::integral_constant<int, 0>{});
