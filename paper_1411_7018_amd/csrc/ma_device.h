@@ -268,8 +268,20 @@ __device__ __forceinline__ double smallest_root(const Hess &g, double F, bool &n
     // then sends the rest (a non-SPD Hessian, no settling yet, a non-finite
     // iterate, F <= 0) down the full rule, which redoes the start where it
     // differs.  A wavefront whose lanes all settle takes no other branch.
-    double thr = 1e-9 * (fabs(I1) + fabs(sig));
-    double dprev = newton();
+    // From sig = 0 the first step's cubic and slope are c0 and -I2 (the
+    // general expressions give exactly these for finite invariants; a
+    // non-finite one makes the second step non-finite and takes the full
+    // rule), and the threshold is 1e-9 |I1|.
+    double thr = 1e-9 * fabs(I1);
+    double dprev;
+    {
+        const double dq = -I2;
+        double r = __builtin_amdgcn_rcp(dq);
+        r = fma(r, fma(-dq, r, 1.0), r);
+        const double d = c0 * r;
+        sig = -d;
+        dprev = fabs(d);
+    }
     double ad = newton();
     bool settled = test(ad, dprev, thr);
     if (!((F > 0.0) & spd & settled & bool(isfinite(sig)))) {
