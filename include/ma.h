@@ -98,9 +98,12 @@ typedef struct {
     int profile;           /* 1: time finest-level smoothing with HIP events     */
     int tile_config;       /* block sweep shape: 0 automatic, 1..7 fixed (8^3
                               blocks of 256, 512, 1024 threads; 16x8x4 of 256;
-                              16x16x8 of 512; 8x8x4 of 512, 256); 8..11 the
+                              16x16x8 of 512; 8x8x4 of 512, 256); 8..12 the
                               z-stream sweep's columns (32x26 of 1024, 512
-                              threads, 32x26 with twice the chunks, 40x20)     */
+                              threads, 32x26 with twice the chunks, 40x20,
+                              32x24 with one colour per wavefront); on
+                              z-stream levels 0 picks 32x26 or 32x24 by a
+                              model of the chunks' rounds                     */
     int block_n;           /* MA_SMOOTHER_AUTO: block sweeps on levels with
                               n <= block_n; 0 automatic (64), -1 never          */
     int graphs;            /* 1: replay each cycle from a captured hipGraph      */

@@ -21,13 +21,18 @@ struct BCfg {
 // threads per block cut the rounds of updates per phase, which is what a
 // sweep of a small grid waits on.  Z-stream sweeps (tz unused): TX x TY
 // columns whose update items (TX TY + 3 (TX + TY) + 14 per step) nearly
-// fill the workgroup once or twice; the planes are cut into chunks, by the
-// model of zs_chunks or into about zwg workgroups (one per compute unit at
-// a time, the ring filling most of the LDS).
+// fill the workgroup once or twice; 32 x 24 fills 1024 items with one
+// colour per wavefront, which makes the colour's plane and ring slots
+// scalars (a step about 2% faster than 32 x 26 with its two mixed
+// wavefronts).  The planes are cut into chunks, by the model of zs_chunks
+// or into about zwg workgroups (one per compute unit at a time, the ring
+// filling most of the LDS).
 constexpr BCfg kCfg[] = {{8, 8, 8, 256, 0},   {8, 8, 8, 512, 0},  {8, 8, 8, 1024, 0},
                          {16, 8, 4, 256, 0},  {16, 16, 8, 512, 0}, {8, 8, 4, 512, 0},
                          {8, 8, 4, 256, 0},   {32, 26, 0, 1024, -1}, {32, 26, 0, 512, -1},
-                         {32, 26, 0, 1024, 1536}, {40, 20, 0, 1024, -1}};
+                         {32, 26, 0, 1024, 1536}, {40, 20, 0, 1024, -1},
+                         {32, 24, 0, 1024, -1}};
+constexpr int kZsPureConfig = 11;
 
 // Compute units of the current device (one z-stream workgroup each at a time).
 int device_cus()
@@ -68,6 +73,21 @@ int zs_chunks(int n, int cols)
     return best;
 }
 constexpr int kNumCfg = int(sizeof(kCfg) / sizeof(kCfg[0]));
+
+// Automatic z-stream shape of an n grid: 32 x 26 or the one-colour-per-
+// wavefront 32 x 24, whichever the chunk model (rounds x (planes + 10) step
+// times, the 32 x 24 step counted 2% shorter) gives the shorter sweep.  At
+// n = 256 the 88 columns of 32 x 24 make three chunks one workgroup too
+// many per compute unit, where the 80 of 32 x 26 fit.
+int zs_model_cost100(int n, int cfg)
+{
+    const BCfg &b = kCfg[cfg];
+    const int cols = ((n - 1 + b.tx - 1) / b.tx) * ((n - 1 + b.ty - 1) / b.ty);
+    const int zc = zs_chunk(n, zs_chunks(n, cols));
+    const long t = (n - 1 + zc - 1) / zc;
+    const long rounds = (long(cols) * t + device_cus() - 1) / device_cus();
+    return int(rounds * (zc + 10) * (cfg == kZsPureConfig ? 98 : 100));
+}
 
 template <int OP, int TX, int TY, int NT>
 hipError_t zgo_list(hipStream_t st, const FsList *L, int blocks, unsigned long long *nc, bool pro)
@@ -131,6 +151,8 @@ hipError_t list_op(int cfg, hipStream_t st, const FsList *L, int blocks, unsigne
         return zgo_list<OP, 32, 26, 512>(st, L, blocks, nc, pro);
     case 10:
         return zgo_list<OP, 40, 20, 1024>(st, L, blocks, nc, pro);
+    case 11:
+        return zgo_list<OP, 32, 24, 1024>(st, L, blocks, nc, pro);
     default:
         return hipErrorInvalidValue;
     }
@@ -161,6 +183,8 @@ hipError_t one_op(int cfg, hipStream_t st, const FsGrid &G, unsigned long long *
         return zgo_one<OP, 32, 26, 512>(st, G, nc);
     case 10:
         return zgo_one<OP, 40, 20, 1024>(st, G, nc);
+    case 11:
+        return zgo_one<OP, 32, 24, 1024>(st, G, nc);
     default:
         return hipErrorInvalidValue;
     }
@@ -186,6 +210,13 @@ int bsweep_pick(int n, long tiles8)
     if (n <= 64)
         return 0;
     return 4;
+}
+
+// Automatic z-stream shape (config index) of an n grid: the cheaper of
+// 32 x 26 and 32 x 24 by the chunk model.
+int bsweep_zs_pick(int n)
+{
+    return zs_model_cost100(n, kZsPureConfig) <= zs_model_cost100(n, 7) ? kZsPureConfig : 7;
 }
 
 void bsweep_grid(int cfg, int n, const double *uin, double *uout, const double *F, int op,

@@ -1560,7 +1560,7 @@ bool Engine::block_level(int n, Mode mode) const
 
 // Automatic choice (zsweep_n = 0), from whole-solve timings on MI355X: the
 // z-stream sweep moves each node once per sweep but recomputes ~23% of the
-// updates and waits on its barriers, and a grid needs enough 32 x 26
+// updates and waits on its barriers, and a grid needs enough 32 x 24
 // columns to give every compute unit a chunk of planes; with the
 // prolongation folded into the first post-smoothing sweep it pays from
 // n = 192 (385^3 solve 68.8 -> 66.7 ms with level 192 as z-stream sweeps;
@@ -1893,14 +1893,14 @@ ma_status Engine::rebuild(Mode mode, const std::vector<char> &active)
                 const long t = (n - 1 + 7) / 8;
                 tiles8 += t * t * t;
             }
-            // z-stream levels take a z-stream shape (tile_config 8..11, else
-            // the first), the others a block shape (tile_config 1..7, else
-            // the automatic pick)
+            // z-stream levels take a z-stream shape (tile_config 8..12, else
+            // the automatic pick), the others a block shape (tile_config
+            // 1..7, else the automatic pick)
             const bool zs = zs_level(nmax, mode) ||
                             (smoother_ == MA_SMOOTHER_FUSED && tile_config_ > kZsFirstConfig);
             int cfg;
             if (zs)
-                cfg = tile_config_ >= kZsFirstConfig + 1 ? tile_config_ - 1 : kZsFirstConfig;
+                cfg = tile_config_ >= kZsFirstConfig + 1 ? tile_config_ - 1 : bsweep_zs_pick(nmax);
             else if (tile_config_ > 0 && tile_config_ <= kZsFirstConfig)
                 cfg = tile_config_ - 1;
             else

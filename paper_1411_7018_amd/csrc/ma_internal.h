@@ -34,6 +34,8 @@ int bsweep_num_configs();
 // Automatic block shape for grids of up to n intervals whose 8^3 tiles number
 // tiles8 in all.
 int bsweep_pick(int n, long tiles8);
+// automatic z-stream shape (config index) of an n grid
+int bsweep_zs_pick(int n);
 
 // --- residual and norm ----------------------------------------------------
 // r = F - S(u) (interior; 0 on the boundary; r may be null) and per-block sums

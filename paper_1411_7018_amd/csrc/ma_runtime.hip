@@ -52,7 +52,7 @@ bool valid_params(const ma_params *p, std::string &why)
     }
     if (p->tile_config < 0 || p->tile_config > bsweep_num_configs() || p->block_n < -1 ||
         p->block_n > 2048) {
-        why = "tile_config must be in 0..11 and block_n in -1..2048";
+        why = "tile_config must be in 0..12 and block_n in -1..2048";
         return false;
     }
     if (p->max_cycles < 0 || p->init_max_cycles < 0 || p->inner_cycles < 1 ||

@@ -67,17 +67,25 @@ struct ZsShape {
     static constexpr int ncol(int c) { return TX / 2 + 3 - c; }
     static constexpr int nrow(int c) { return TY / 2 + 3 - c; }
     static constexpr int count(int c) { return ncol(c) * nrow(c); }
-    // Update items: colours 0 and 1, then colours 2 and 3 from the next
-    // whole wavefront on.  A colour-c node at plane P has x parity
-    // (c >> 1) + P mod 2 and P has the step's parity, so the x parity -- and
-    // with it the LDS offsets of the x neighbours -- is the same across
-    // every wavefront.
+    // Update items.  When every colour can start on a whole wavefront
+    // within 1024 items (pure), each wavefront updates one colour and the
+    // colour is uniform across it; else colours 0 and 1, then colours 2 and
+    // 3 from the next whole wavefront on.  A colour-c node at plane P has x
+    // parity (c >> 1) + P mod 2 and P has the step's parity, so the x parity
+    // -- and with it the LDS offsets of the x neighbours -- is the same
+    // across every wavefront either way.
+    static constexpr int pad64(int x) { return (x + 63) / 64 * 64; }
+    static constexpr bool pure = pad64(count(0)) + pad64(count(1)) + pad64(count(2)) + count(3) <= 1024;
     static constexpr int first(int c)
     {
-        return c == 0 ? 0
+        return pure ? (c == 0 ? 0
+                       : c == 1 ? pad64(count(0))
+                       : c == 2 ? pad64(count(0)) + pad64(count(1))
+                                : pad64(count(0)) + pad64(count(1)) + pad64(count(2)))
+               : c == 0 ? 0
                : c == 1 ? count(0)
-               : c == 2 ? (count(0) + count(1) + 63) / 64 * 64
-                        : (count(0) + count(1) + 63) / 64 * 64 + count(2);
+               : c == 2 ? pad64(count(0) + count(1))
+                        : pad64(count(0) + count(1)) + count(2);
     }
     static constexpr int items = first(3) + count(3);
     static constexpr size_t lds_bytes() { return size_t(NL) * sizeof(double); }
@@ -314,7 +322,7 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
         int c = -1;
         if (q < S::first(0) + S::count(0))
             c = 0;
-        else if (q < S::first(1) + S::count(1))
+        else if (q >= S::first(1) && q < S::first(1) + S::count(1))
             c = 1;
         else if (q >= S::first(2) && q < S::first(2) + S::count(2))
             c = 2;
@@ -370,9 +378,14 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
     // it is too, and each side reads its neighbours at constant offsets.
     auto update = [&](int m, int s, int rs, double f) {
         const int sp = s & 1;
-        const int c = ic[m];
+        // one colour per wavefront (pure): read it from the first lane, so
+        // the plane, its range and the ring slots below are scalars (the
+        // items past a colour's count, c = -1, are never active)
+        const int c = S::pure ? __builtin_amdgcn_readfirstlane(ic[m]) : ic[m];
         const int P = s - 2 * c;
-        if (!active(m, sp, P))
+        const bool in_planes = S::pure ? P >= max(1, z0 - 3 + c) && P <= min(n - 1, z1 + 2 - c)
+                                       : P >= plo[m] && P <= phi[m];
+        if (!(okxy[m][sp] && in_planes))
             return;
         const int io = lio[m][sp];
         // ring slots of planes P, P - 1, P + 1 from the step's slot rs =

@@ -78,7 +78,7 @@ def test_create_rejects_invalid_params_without_gpu():
     from paper_1411_7018_amd import _lib as L
     for field, val in (("n", 1), ("nu0", 0), ("order", 7), ("precision", 9),
                        ("restriction", 5), ("inner_cycles", 0), ("smoother", 3),
-                       ("tile_config", 12), ("tile_config", -1), ("block_n", -2),
+                       ("tile_config", 13), ("tile_config", -1), ("block_n", -2),
                        ("coarse_n", 33), ("max_blocks", 12), ("strip_rows", 5000),
                        ("zsweep_n", -2), ("zsweep_n", 4096), ("fuse_prolong", 1),
                        ("fuse_prolong", -2)):

@@ -47,8 +47,8 @@ def start(p, seed):
 
 
 # ragged grids (n - 1 not a multiple of the block sides) and tiny ones;
-# configurations 8..11 are the z-stream sweeps
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11])
+# configurations 8..12 are the z-stream sweeps
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("n", [2, 4, 9, 33, 47, 64, 100])
 def test_block_sweep_bitwise_vs_color_and_oracle(n, cfg):
     note("block sweep", n, cfg)

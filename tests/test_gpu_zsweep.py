@@ -15,7 +15,7 @@ from paper_1411_7018_amd import problems as P
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-ZS_CONFIGS = (8, 9, 10, 11)
+ZS_CONFIGS = (8, 9, 10, 11, 12)
 
 
 def note(*args):
@@ -68,6 +68,7 @@ def _solve(n, kind, seed, **kw):
     (96, "exp_cos", {"smoother": "fused", "tile_config": 9}),
     (128, "exp_cos", {"smoother": "fused", "tile_config": 10}),
     (64, "exp_cos", {"smoother": "fused", "tile_config": 11}),
+    (160, "exp_cos", {"smoother": "fused", "tile_config": 12}),  # one colour per wavefront
 ])
 def test_fused_prolongation_solve_bitwise(n, kind, kw):
     """Solves whose first post-smoothing z-stream sweep also applies the
