@@ -45,7 +45,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by the same counter's reading for a plain copy of
 # known size), keyed by (workload, kernel); valid only for the kernel as it
 # was profiled.
-TRAFFIC = {("served", "k_zsweep"): 1.788e9}   # profiles/k_zsweep_expcos385.md
+TRAFFIC = {("served", "k_zsweep"): 1.785e9}   # profiles/k_zsweep_expcos385.md
 METRIC = "solves/s + p50/p99 latency at 1e-8 rel residual; smoother GB/s vs HBM peak"
 SINGLE = {
     # name: (kind, n, seed, tol, start)
