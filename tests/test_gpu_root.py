@@ -83,3 +83,23 @@ def test_regular_node_unchanged_and_not_counted():
     sg, so, count = _sigma_pair(M, 0.9 * np.linalg.det(M))
     assert count == 0
     assert abs(sg - so) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_indefinite_hessian_gershgorin_start(seed):
+    """An indefinite discrete Hessian with F > 0: the rule starts Newton from
+    the Gershgorin lower bound of lambda_min minus F^(1/3) (the start where the
+    SPD test fails) and must still reach the root below lambda_min (Theorem
+    2.2) to round-off, the oracle's closed form agreeing, and without being
+    counted as non-convex."""
+    print("[case] root indefinite", seed, file=sys.stderr, flush=True)
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    M = (q * np.array([-1.0, 0.5, 2.0])[None, :]) @ q.T
+    M = 0.5 * (M + M.T)
+    sg, so, count = _sigma_pair(M, 0.7)
+    lmin = np.linalg.eigvalsh(M)[0]
+    assert count == 0
+    assert sg < lmin and so < lmin
+    assert abs(sg - so) <= 1e-12 * max(1.0, abs(so))
