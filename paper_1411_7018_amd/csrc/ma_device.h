@@ -221,10 +221,11 @@ __device__ __noinline__ double gershgorin_start(Hess g, double F)
 // The Newton quotient uses the hardware reciprocal as it is (relative error
 // below 5e-8 on gfx950, measured over 4M random operands): an inexact
 // quotient scales a step by 1 + eps, which leaves the iteration's fixed point
-// where it is, and at the stop below the error the step leaves under
-// eps x 1e-9 of the scale, i.e. round-off.  Stop when the step is below 1e-9 of
-// the eigenvalue scale AND below 1e-3 of the previous step: in the quadratic
-// phase the error after such a step is O(step^2 / scale), i.e. at round-off.
+// where it is, and at the stop below (a step under 1e-9 of the scale) the
+// error it leaves is under eps x 1e-9 of the scale, i.e. round-off.  Stop
+// when the step is below 1e-9 of the eigenvalue scale AND below 1e-3 of the
+// previous step: in the quadratic phase the error after such a step is
+// O(step^2 / scale), i.e. at round-off.
 // The test starts after the second step: nearly every node needs two steps
 // (one to reach the root, one to show it has), a second step from a root
 // moves it by round-off at most, and in a wavefront the two steps then run
