@@ -368,8 +368,13 @@ __device__ __forceinline__ void zsweep_tile(const FsGrid &G, int tile, double *_
                                7u * plane_bytes);
 #pragma unroll
         for (int m = 0; m < MI; ++m) {
-            const int P = s - 2 * ic[m];
-            f[m] = buf_load(r, active(m, sp, P) ? gio[m][sp] : kBufOob);
+            // one colour per wavefront (pure): its plane and range are scalars
+            const int c = S::pure ? __builtin_amdgcn_readfirstlane(ic[m]) : ic[m];
+            const int P = s - 2 * c;
+            const bool ok = S::pure ? okxy[m][sp] && P >= max(1, z0 - 3 + c) &&
+                                          P <= min(n - 1, z1 + 2 - c)
+                                    : active(m, sp, P);
+            f[m] = buf_load(r, ok ? gio[m][sp] : kBufOob);
         }
     };
 
